@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched orthonormal 2D DCT on one MI355X.
+
+Workload (one "step"): the six square sizes N = 8, 16, 32, 64, 128, 256, each a batch
+of 2^27 / N^2 row-major float32 arrays (512 MiB) of seeded N(0,1) values resident in
+HBM, transformed in place by the forward, inverse and fused round-trip calls of the C
+ABI (18 calls).  Algorithmic traffic is one float32 read and one float32 write per
+element per call (8 N^2 bytes per array), so the step moves 18 x 1 GiB.
+
+Reported: whole-step GB/s, per-size/per-direction GB/s and %HBM, the roofline of the
+dominant kernel (HIP-event timing on the stream the kernels run on), a float32 vs
+split-precision matrix-path comparison where it exists, and the FP64 oracle timed on a
+bounded sample of the same arrays on the host cores (the CPU baseline).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "2D DCT GB/s & %HBM peak, N=8..256 fp32; split-BF16 MFMA vs plain FP32"
+HBM_PEAK_GBS = 8000.0
+SIZES = (8, 16, 32, 64, 128, 256)
+DIRS = ("forward", "inverse", "roundtrip")
+GATE = {"forward": 2e-6, "inverse": 2e-6, "roundtrip": 4e-6}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sizes", default=",".join(map(str, SIZES)))
+    ap.add_argument("--precision", default="auto", help="path used by the step (auto = library default)")
+    ap.add_argument("--compare", default="fp32,bf16x3,bf16x6,fp16x3",
+                    help="paths timed per size for the float32 vs split comparison (N<=32 for splits)")
+    ap.add_argument("--cpu-frac", type=float, default=0.25, help="fraction of each batch the oracle runs on")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--log2-floats", type=int, default=27, help="floats per size (default 2^27 = 512 MiB)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the batched transform needs no communication, "
+              "a multi-GPU run would be N independent copies of this one (see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2609_28519_amd as dct
+    import workloads
+
+    sizes = [int(s) for s in args.sizes.split(",") if s]
+    dct.init(0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+
+    # ---- inputs resident in HBM ------------------------------------------------------
+    host = {}
+    bufs = {}
+    for n in sizes:
+        batch = (1 << args.log2_floats) // (n * n)
+        x = workloads.c3_normal(n, batch=batch).x
+        host[n] = x
+        bufs[n] = torch.from_numpy(x).to(dev)
+        print("input N=%d batch=%d (%.0f MiB)" % (n, batch, x.nbytes / 2 ** 20), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+
+    def call(n, d, prec, t):
+        return dct.transform(t, t, d, prec, stream=stream)
+
+    # ---- self-check before timing (round trip must return the input) -----------------
+    for n in sizes:
+        t = bufs[n][:64].clone()
+        x0 = t.clone()
+        call(n, "roundtrip", args.precision, t)
+        torch.cuda.synchronize()
+        num = torch.linalg.vector_norm((t - x0).double().reshape(64, -1), dim=1)
+        den = torch.linalg.vector_norm(x0.double().reshape(64, -1), dim=1)
+        worst = float((num / den).max())
+        if worst > GATE["roundtrip"]:
+            print("self-check failed N=%d e_rel %.3e" % (n, worst), file=sys.stderr)
+            sys.exit(1)
+
+    # ---- warmup + timed steps ----------------------------------------------------------
+    for _ in range(args.warmup):
+        for n in sizes:
+            for d in DIRS:
+                call(n, d, args.precision, bufs[n])
+    torch.cuda.synchronize()
+    ev = {(n, d): [] for n in sizes for d in DIRS}
+    step_start = torch.cuda.Event(enable_timing=True)
+    step_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step_start.record(stream)
+    for _ in range(args.steps):
+        for n in sizes:
+            for d in DIRS:
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                call(n, d, args.precision, bufs[n])
+                b.record(stream)
+                ev[(n, d)].append((a, b))
+    step_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = step_start.elapsed_time(step_end)
+    ms_per_step = total_ms / args.steps
+    bytes_per_step = sum(8 * n * n * host[n].shape[0] for n in sizes) * len(DIRS)
+    value = bytes_per_step / (ms_per_step * 1e-3) / 1e9
+
+    per = {}
+    call_ms = {}
+    for n in sizes:
+        per[str(n)] = {}
+        for d in DIRS:
+            ms = float(np.mean([a.elapsed_time(b) for a, b in ev[(n, d)]]))
+            call_ms[(n, d)] = ms
+            gbs = 8 * n * n * host[n].shape[0] / (ms * 1e-3) / 1e9
+            per[str(n)][d] = {"ms": round(ms, 4), "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                              "transforms_per_s": round(host[n].shape[0] / (ms * 1e-3), 1)}
+
+    # dominant kernel: the call with the largest share of the step among single-kernel calls
+    single = [(n, d) for n in sizes for d in DIRS if n <= 128]
+    dom = max(single, key=lambda k: call_ms[k]) if single else max(call_ms, key=call_ms.get)
+    n_dom, d_dom = dom
+    alg_bytes = 8 * n_dom * n_dom * host[n_dom].shape[0]
+    achieved = alg_bytes / (call_ms[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "fused fp32 %s N=%d" % (d_dom, n_dom), "avg_ms": round(call_ms[dom], 4),
+                "algorithmic_bytes_per_launch": alg_bytes}
+
+    # ---- float32 vs split-precision matrix paths (same GPU, same inputs) --------------
+    compare = {}
+    for p in [c for c in args.compare.split(",") if c]:
+        for n in sizes:
+            if p != "fp32" and n > 64:
+                continue
+            scratch = torch.empty_like(bufs[n])
+            try:
+                dct.transform(bufs[n], scratch, "forward", p, stream=stream)
+            except dct.DCT2DError:
+                continue
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            reps = 5
+            a.record(stream)
+            for _ in range(reps):
+                dct.transform(bufs[n], scratch, "forward", p, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            compare.setdefault(p, {})[str(n)] = round(8 * n * n * host[n].shape[0] / (ms * 1e-3) / 1e9, 1)
+            del scratch
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "six square sizes N=8..256, 2^%d float32 per size (batch 2^%d/N^2), N(0,1); "
+                                  "forward + inverse + fused round trip, in place" % (args.log2_floats,
+                                                                                     args.log2_floats),
+                      "sizes": sizes, "batch": {str(n): int(host[n].shape[0]) for n in sizes},
+                      "precision": args.precision},
+           "hbm_frac": round(value / HBM_PEAK_GBS, 4), "wall_s": round(wall, 3),
+           "roofline": roofline, "per_size": per, "compare_forward_GBps": compare}
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample of the same arrays -----------
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(host, sizes, args.cpu_frac, bufs, stream)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(host, sizes, frac, bufs, stream):
+    """Times the FP64 oracle (as it stands) on the first `frac` of every size's arrays, on the host's
+    cores, for forward, inverse and round trip; also scores the GPU forward of that sample."""
+    import torch
+
+    import oracle
+    import paper_2609_28519_amd as dct
+
+    threads = oracle.default_threads()
+    total_bytes = 0
+    total_s = 0.0
+    worst = {}
+    for n in sizes:
+        m = max(1, int(host[n].shape[0] * frac))
+        xs = host[n][:m]
+        t0 = time.perf_counter()
+        y = oracle.forward(xs, threads=threads)
+        oracle.inverse(xs, threads=threads)
+        oracle.roundtrip(xs, threads=threads)
+        total_s += time.perf_counter() - t0
+        total_bytes += 8 * n * n * m * 3
+        # error of the GPU forward on part of the sample, vs the oracle (stated for every result)
+        k = min(m, 256)
+        g = torch.from_numpy(xs[:k]).cuda()
+        dct.transform(g, g, "forward", "auto", stream=stream)
+        torch.cuda.synchronize()
+        worst[str(n)] = float(oracle.e_rel(g.cpu().numpy(), y[:k], xs[:k]).max())
+    return {"value": round(total_bytes / total_s / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": "first %.0f%% of each size's batch (forward + inverse + round trip, FP64 direct definition)"
+                      % (100 * frac),
+            "seconds": round(total_s, 2), "gpu_forward_max_e_rel_vs_oracle": worst}
+
+
+if __name__ == "__main__":
+    main()

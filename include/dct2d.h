@@ -1,0 +1,186 @@
+/*
+ * dct2d.h -- C ABI of the MI355X (gfx950) batched orthonormal 2D DCT library.
+ *
+ * The operation (paper, Section 2.1, eq. 1 and eq. 2; rectangles Section 7.1):
+ *   (Q_n)_{kj} = a_k cos(pi/n (j + 1/2) k),   a_0 = n^{-1/2},  a_k = (2/n)^{1/2}
+ *   forward   Y = Q_h X Q_w^T      (2D DCT-II, orthonormal)
+ *   inverse   X = Q_h^T Y Q_w      (2D DCT-III, the Frobenius adjoint of the forward)
+ *   roundtrip X' = Q_h^T (Q_h X Q_w^T) Q_w, fused in one pass over memory (Section 3.1,
+ *             Prop. 1); its exact result is X.
+ * "Exact" in the paper's sense (Section 1.1): no truncated coefficients and no
+ * approximate matrix; floating-point results differ from real arithmetic only by
+ * rounding and are not bit-identical across algorithms.
+ *
+ * Data layout (all entry points): an array of `batch` row-major float32 arrays of
+ * rows x cols elements.  Array b starts at element b*stride of the buffer; inside an
+ * array, element (r, c) is at r*cols + c (rows contiguous, pitch = cols).  This is the
+ * paper's "ordinary row-major" natural layout (Section 1.1, Section 3.1).  `stride` is
+ * counted in floats and must be >= rows*cols, so arrays never overlap.
+ *
+ * Pointers: `data`, `in`, `out` and ragged `base` are DEVICE pointers (memory the
+ * caller allocated on the current HIP device, e.g. through PyTorch).  The caller
+ * owns them; the library never frees or retains them past the call, except that a
+ * ragged plan remembers nothing about them either -- the base pointer is passed to
+ * every execute call.  Host pointers are accepted only where stated (descriptor
+ * arrays of the ragged planner).
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ * transform calls only enqueue work and return; results are visible after the
+ * caller synchronises that stream.  Return codes cover argument validation and
+ * launch errors; a fault during execution surfaces at the caller's synchronisation.
+ *
+ * Sizes accepted by the three basic calls and dct2d_transform_ex: rows and cols each
+ * a power of two in [8, 256] (squares and rectangles).  Any other length returns
+ * DCT2D_ERR_SIZE: like the paper (Section 7.1) the basic API rejects
+ * non-power-of-two axes instead of zero-padding, which would change the transform.
+ * Ragged plans additionally accept whole images with axes up to 1024, including
+ * non-power-of-two lengths (computed exactly from the dense Q_n of eq. 1).
+ *
+ * Alignment: `data`/`in`/`out` must be 16-byte aligned and strides multiples of 4
+ * floats (DCT2D_ERR_ALIGN otherwise).
+ *
+ * Errors are returned, never thrown, and the library never aborts the process.
+ * Thread safety: after dct2d_init, the transform calls may be issued from several
+ * host threads; a ragged plan must not be executed concurrently with itself.
+ * No call allocates device memory or plans anything after dct2d_init (Section 3.2:
+ * plan-owned tables and workspace, no allocation inside a transform), except that
+ * the first call on a device initialises it if dct2d_init was not called.
+ */
+#ifndef DCT2D_H
+#define DCT2D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------ */
+#define DCT2D_OK             0
+#define DCT2D_ERR_ARG       -1  /* null pointer with batch > 0, batch < 0, bad enum */
+#define DCT2D_ERR_SIZE      -2  /* unsupported rows/cols                           */
+#define DCT2D_ERR_STRIDE    -3  /* stride < rows*cols                               */
+#define DCT2D_ERR_ALIGN     -4  /* pointer not 16-byte aligned / stride % 4 != 0     */
+#define DCT2D_ERR_PRECISION -5  /* precision not available for this size            */
+#define DCT2D_ERR_HIP       -6  /* a HIP runtime call or kernel launch failed        */
+#define DCT2D_ERR_NOINIT    -7  /* no usable device / library not initialised        */
+#define DCT2D_ERR_NOMEM     -8  /* device or host allocation failed (init, plans)    */
+
+/* ---- directions ---------------------------------------------------------------- */
+#define DCT2D_FORWARD   0   /* Y = Q_h X Q_w^T            (eq. 2)                  */
+#define DCT2D_INVERSE   1   /* X = Q_h^T Y Q_w            (eq. 2)                  */
+#define DCT2D_ROUNDTRIP 2   /* inverse(forward(X)), fused (Section 3.1, Prop. 1)   */
+
+/* ---- arithmetic paths ------------------------------------------------------------
+ * DCT2D_FP32        float32 fast transforms on the vector ALU (all sizes).
+ * DCT2D_SPLIT_BF16X3  dense Q X Q^T on MFMA, bf16 two-way split of Q and X, three
+ *                   products (hi*hi + hi*lo + lo*hi), fp32 accumulation, per-block
+ *                   power-of-two scaling.  rows = cols <= 32.  Not float32-accurate
+ *                   (~16 significant bits); reported, not gated.
+ * DCT2D_SPLIT_BF16X6  as above with a three-way bf16 split and the six products
+ *                   whose split indices sum to <= 2; float32-accurate.
+ * DCT2D_SPLIT_FP16X3  fp16 two-way split, three products, per-block power-of-two
+ *                   scaling before each pass; float32-accurate for finite inputs.
+ * DCT2D_BF16 / DCT2D_FP16 / DCT2D_FP8_E4M3  single-pass low precision on MFMA with
+ *                   per-block power-of-two scaling (error reported, never gated).
+ * DCT2D_AUTO        the library's frozen per-size choice among the float32-accurate
+ *                   paths (FP32, SPLIT_BF16X6, SPLIT_FP16X3). */
+typedef enum {
+    DCT2D_FP32 = 0,
+    DCT2D_SPLIT_BF16X3 = 1,
+    DCT2D_SPLIT_BF16X6 = 2,
+    DCT2D_SPLIT_FP16X3 = 3,
+    DCT2D_BF16 = 4,
+    DCT2D_FP16 = 5,
+    DCT2D_FP8_E4M3 = 6,
+    DCT2D_AUTO = 7
+} dct2d_precision;
+
+/* Initialise the library on HIP device `device` (0-based): generates the cosine,
+ * twiddle and split tables on that device in FP64 (the only FP64 work on the GPU)
+ * and rounds them to the formats the kernels read.  Idempotent; safe to call again.
+ * Returns DCT2D_OK, DCT2D_ERR_NOINIT (no such device) or DCT2D_ERR_HIP/NOMEM. */
+int dct2d_init(int device);
+
+/* Release every device's tables.  Plans must be destroyed first. */
+void dct2d_finalize(void);
+
+/* In-place forward transform of `batch` arrays at `data` (device pointer), using the
+ * library's default float32-accurate path (DCT2D_AUTO).  batch == 0 is a no-op. */
+int dct2d_forward(float* data, int64_t batch, int32_t rows, int32_t cols, int64_t stride,
+                  void* stream);
+
+/* In-place inverse transform (eq. 2, DCT-III).  Same arguments and rules. */
+int dct2d_inverse(float* data, int64_t batch, int32_t rows, int32_t cols, int64_t stride,
+                  void* stream);
+
+/* In-place fused round trip inverse(forward(X)): one read and one write of each array. */
+int dct2d_roundtrip(float* data, int64_t batch, int32_t rows, int32_t cols, int64_t stride,
+                    void* stream);
+
+/* General entry: direction `dir` (DCT2D_FORWARD/INVERSE/ROUNDTRIP), out-of-place or
+ * in-place (in == out allowed; partially overlapping buffers are not), explicit
+ * arithmetic path `precision` (dct2d_precision).  in_stride / out_stride as above.
+ * Returns DCT2D_ERR_PRECISION when the path does not exist for the size. */
+int dct2d_transform_ex(int dir, const float* in, float* out, int64_t batch, int32_t rows,
+                       int32_t cols, int64_t in_stride, int64_t out_stride, int precision,
+                       void* stream);
+
+/* ---- ragged batches: many arrays of different shapes in one launch ------------------
+ * A descriptor names one array inside a caller buffer: its first element is at
+ * base + offset (floats), its shape rows x cols (pitch = cols).  Arrays must not
+ * overlap.  Square blocks 8..256 (powers of two) and whole images with each axis in
+ * [8, 1024] are accepted.
+ *
+ * dct2d_ragged_plan_create copies the (host) descriptor array, sorts the items into
+ * size classes, uploads the work lists to the device, picks a kernel configuration
+ * per class from the autotuner's frozen table, and records the whole batch as one
+ * HIP graph.  It allocates device memory (once, here).  `dir` is a DCT2D_* direction,
+ * `precision` a dct2d_precision (float32-accurate paths only).
+ *
+ * dct2d_ragged_execute runs the plan on the arrays at `base` (device pointer, 16-byte
+ * aligned) with one hipGraphLaunch on `stream`, in place.  Offsets must be multiples
+ * of 4.  It allocates nothing.
+ */
+typedef struct {
+    int64_t offset;  /* element offset from base (multiple of 4) */
+    int32_t rows;    /* array height */
+    int32_t cols;    /* array width (= pitch) */
+} dct2d_block;
+
+typedef struct dct2d_ragged_plan dct2d_ragged_plan;
+
+int dct2d_ragged_plan_create(const dct2d_block* blocks, int64_t count, int dir, int precision,
+                             dct2d_ragged_plan** out_plan);
+int dct2d_ragged_execute(dct2d_ragged_plan* plan, float* base, void* stream);
+void dct2d_ragged_plan_destroy(dct2d_ragged_plan* plan);
+
+/* Number of kernel launches recorded in the plan's graph (diagnostics). */
+int dct2d_ragged_plan_info(const dct2d_ragged_plan* plan, int64_t* items, int32_t* classes,
+                           int32_t* graph_nodes);
+
+/* ---- policy / autotuner ----------------------------------------------------------------
+ * The per-(rows, cols, dir, precision) kernel configuration is a small integer
+ * "variant" chosen by the autotuner ahead of time and frozen (Section 3.2: variants
+ * fixed per size and direction before measurement).  dct2d_tune measures the
+ * candidate variants for one case on scratch data it allocates itself (call it
+ * outside timed regions) and freezes the fastest one that passes the library's own
+ * self-consistency check; dct2d_get_variant / dct2d_set_variant read and override the
+ * frozen table; dct2d_variant_count gives the number of candidates (0 = none). */
+int dct2d_variant_count(int32_t rows, int32_t cols, int dir, int precision);
+int dct2d_get_variant(int32_t rows, int32_t cols, int dir, int precision);
+int dct2d_set_variant(int32_t rows, int32_t cols, int dir, int precision, int variant);
+int dct2d_tune(int32_t rows, int32_t cols, int dir, int precision, int64_t batch, void* stream,
+               float* best_ms);
+
+/* Human-readable text for a status code (static storage). */
+const char* dct2d_status_string(int status);
+
+/* Library version string (static storage). */
+const char* dct2d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCT2D_H */

@@ -1,0 +1,282 @@
+// C ABI of the library (include/dct2d.h): argument validation, the frozen per-size
+// policy, dispatch to the kernel families, and the autotuner.
+//
+// Validation happens once per call on the host, never per block (the paper's
+// argument-check-free control, Section 5.1, shows checks must stay off the hot path).
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace dct;
+
+namespace {
+
+constexpr int kNumPrec = 8;
+
+// Frozen variant table: index [log2 rows - 3][log2 cols - 3][dir][precision]; -1 = default 0.
+std::mutex g_policy_mu;
+int g_variant[6][6][3][kNumPrec];
+bool g_policy_ready = false;
+
+void policy_init_locked()
+{
+    if (g_policy_ready) return;
+    for (auto& a : g_variant)
+        for (auto& b : a)
+            for (auto& c : b)
+                for (int& v : c) v = 0;
+    g_policy_ready = true;
+}
+
+int lg2(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+bool basic_size_ok(int rows, int cols)
+{
+    return is_pow2(rows) && is_pow2(cols) && rows >= 8 && rows <= 256 && cols >= 8 && cols <= 256;
+}
+
+int variant_for(int rows, int cols, int dir, int prec)
+{
+    std::lock_guard<std::mutex> lk(g_policy_mu);
+    policy_init_locked();
+    return g_variant[lg2(rows) - 3][lg2(cols) - 3][dir][prec];
+}
+
+// DCT2D_AUTO: the float32-accurate path chosen per size.  Frozen before measurement
+// (Section 3.2); the plain float32 path unless a split matrix path is registered faster.
+std::atomic<int> g_auto_path[6][6][3];
+std::once_flag g_auto_once;
+
+void auto_init()
+{
+    for (auto& a : g_auto_path)
+        for (auto& b : a)
+            for (auto& c : b) c.store(DCT2D_FP32);
+}
+
+int resolve_precision(int rows, int cols, int dir, int prec)
+{
+    if (prec != DCT2D_AUTO) return prec;
+    std::call_once(g_auto_once, auto_init);
+    return g_auto_path[lg2(rows) - 3][lg2(cols) - 3][dir].load();
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int validate(int dir, const float* in, const float* out, int64_t batch, int32_t rows, int32_t cols,
+             int64_t in_stride, int64_t out_stride, int prec)
+{
+    if (dir < DCT2D_FORWARD || dir > DCT2D_ROUNDTRIP) return DCT2D_ERR_ARG;
+    if (prec < 0 || prec >= kNumPrec) return DCT2D_ERR_ARG;
+    if (batch < 0) return DCT2D_ERR_ARG;
+    if (!basic_size_ok(rows, cols)) return DCT2D_ERR_SIZE;
+    const int64_t n = (int64_t)rows * cols;
+    if (in_stride < n || out_stride < n) return DCT2D_ERR_STRIDE;
+    if (batch == 0) return DCT2D_OK;
+    if (!in || !out) return DCT2D_ERR_ARG;
+    if (!aligned16(in) || !aligned16(out) || (in_stride & 3) || (out_stride & 3)) return DCT2D_ERR_ALIGN;
+    if (in != out) {
+        // partially overlapping buffers are not supported
+        const char* a0 = reinterpret_cast<const char*>(in);
+        const char* a1 = a0 + ((batch - 1) * in_stride + n) * 4;
+        const char* b0 = reinterpret_cast<const char*>(out);
+        const char* b1 = b0 + ((batch - 1) * out_stride + n) * 4;
+        if (a0 < b1 && b0 < a1) return DCT2D_ERR_ARG;
+    }
+    return DCT2D_OK;
+}
+
+int run(int dir, const float* in, float* out, int64_t batch, int32_t rows, int32_t cols, int64_t in_stride,
+        int64_t out_stride, int prec, void* stream)
+{
+    int rc = validate(dir, in, out, batch, rows, cols, in_stride, out_stride, prec);
+    if (rc != DCT2D_OK || batch == 0) return rc;
+    const DeviceTables* t = tables_current(&rc);
+    if (!t) return rc;
+    const int p = resolve_precision(rows, cols, dir, prec);
+    Job j{dir, in, out, batch, rows, cols, in_stride, out_stride, static_cast<hipStream_t>(stream),
+          variant_for(rows, cols, dir, p)};
+    if (p == DCT2D_FP32) return launch_fp32(t, j);
+    if (!mfma_supported(rows, cols, p)) return DCT2D_ERR_PRECISION;
+    return launch_mfma(t, j, p);
+}
+
+int variant_count(int rows, int cols, int dir, int prec)
+{
+    if (prec == DCT2D_FP32) return fp32_variant_count(rows, cols, dir);
+    if (!mfma_supported(rows, cols, prec)) return 0;
+    return mfma_variant_count(rows, cols, dir, prec);
+}
+
+// Deterministic scratch fill for tuning: a counter hash mapped to [-1, 1).
+__global__ void k_fill(float* p, int64_t n, uint32_t seed)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t x = (uint32_t)i * 2654435761u ^ seed;
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    p[i] = (float)(x >> 8) * (2.0f / 16777216.0f) - 1.0f;
+}
+
+} // namespace
+
+extern "C" {
+
+int dct2d_init(int device)
+{
+    const int rc = tables_init_device(device);
+    if (rc != DCT2D_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_policy_mu);
+    policy_init_locked();
+    return DCT2D_OK;
+}
+
+void dct2d_finalize(void) { tables_release_all(); }
+
+int dct2d_forward(float* data, int64_t batch, int32_t rows, int32_t cols, int64_t stride, void* stream)
+{
+    return run(DCT2D_FORWARD, data, data, batch, rows, cols, stride, stride, DCT2D_AUTO, stream);
+}
+
+int dct2d_inverse(float* data, int64_t batch, int32_t rows, int32_t cols, int64_t stride, void* stream)
+{
+    return run(DCT2D_INVERSE, data, data, batch, rows, cols, stride, stride, DCT2D_AUTO, stream);
+}
+
+int dct2d_roundtrip(float* data, int64_t batch, int32_t rows, int32_t cols, int64_t stride, void* stream)
+{
+    return run(DCT2D_ROUNDTRIP, data, data, batch, rows, cols, stride, stride, DCT2D_AUTO, stream);
+}
+
+int dct2d_transform_ex(int dir, const float* in, float* out, int64_t batch, int32_t rows, int32_t cols,
+                       int64_t in_stride, int64_t out_stride, int precision, void* stream)
+{
+    return run(dir, in, out, batch, rows, cols, in_stride, out_stride, precision, stream);
+}
+
+int dct2d_variant_count(int32_t rows, int32_t cols, int dir, int precision)
+{
+    if (!basic_size_ok(rows, cols) || dir < 0 || dir > 2 || precision < 0 || precision >= DCT2D_AUTO) return 0;
+    return variant_count(rows, cols, dir, precision);
+}
+
+int dct2d_get_variant(int32_t rows, int32_t cols, int dir, int precision)
+{
+    if (!basic_size_ok(rows, cols)) return DCT2D_ERR_SIZE;
+    if (dir < 0 || dir > 2 || precision < 0 || precision >= DCT2D_AUTO) return DCT2D_ERR_ARG;
+    return variant_for(rows, cols, dir, precision);
+}
+
+int dct2d_set_variant(int32_t rows, int32_t cols, int dir, int precision, int variant)
+{
+    if (!basic_size_ok(rows, cols)) return DCT2D_ERR_SIZE;
+    if (dir < 0 || dir > 2 || precision < 0 || precision >= DCT2D_AUTO) return DCT2D_ERR_ARG;
+    if (variant < 0 || variant >= variant_count(rows, cols, dir, precision)) return DCT2D_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_policy_mu);
+    policy_init_locked();
+    g_variant[lg2(rows) - 3][lg2(cols) - 3][dir][precision] = variant;
+    return DCT2D_OK;
+}
+
+int dct2d_tune(int32_t rows, int32_t cols, int dir, int precision, int64_t batch, void* stream, float* best_ms)
+{
+    if (!basic_size_ok(rows, cols)) return DCT2D_ERR_SIZE;
+    if (dir < 0 || dir > 2 || precision < 0 || precision >= DCT2D_AUTO || batch <= 0) return DCT2D_ERR_ARG;
+    const int nv = variant_count(rows, cols, dir, precision);
+    if (nv <= 0) return DCT2D_ERR_PRECISION;
+    int rc = DCT2D_OK;
+    const DeviceTables* t = tables_current(&rc);
+    if (!t) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = batch * rows * cols;
+    float *src = nullptr, *dst = nullptr, *ref = nullptr;
+    if (hipMalloc(&src, n * 4) != hipSuccess) return DCT2D_ERR_NOMEM;
+    if (hipMalloc(&dst, n * 4) != hipSuccess) { hipFree(src); return DCT2D_ERR_NOMEM; }
+    if (hipMalloc(&ref, n * 4) != hipSuccess) { hipFree(src); hipFree(dst); return DCT2D_ERR_NOMEM; }
+    k_fill<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, n, 0x5eedu);
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    std::vector<float> host_ref, host_out;
+    int best = -1;
+    float best_t = 0.f;
+    for (int v = 0; v < nv && rc == DCT2D_OK; ++v) {
+        Job j{dir, src, v == 0 ? ref : dst, batch, rows, cols, rows * (int64_t)cols, rows * (int64_t)cols, s, v};
+        auto launch = [&]() {
+            return precision == DCT2D_FP32 ? launch_fp32(t, j) : launch_mfma(t, j, precision);
+        };
+        if ((rc = launch()) != DCT2D_OK) break;
+        if (hipStreamSynchronize(s) != hipSuccess) { rc = DCT2D_ERR_HIP; break; }
+        // self-consistency: every variant must agree with variant 0 to float32 accuracy
+        if (v > 0) {
+            const int64_t m = n < (1 << 20) ? n : (1 << 20);
+            host_ref.resize(m);
+            host_out.resize(m);
+            hipMemcpy(host_ref.data(), ref, m * 4, hipMemcpyDeviceToHost);
+            hipMemcpy(host_out.data(), dst, m * 4, hipMemcpyDeviceToHost);
+            double num = 0, den = 0;
+            for (int64_t i = 0; i < m; ++i) {
+                const double d = (double)host_out[i] - host_ref[i];
+                num += d * d;
+                den += (double)host_ref[i] * host_ref[i];
+            }
+            if (den > 0 && num > 1e-10 * den) continue; // disagrees: never selected
+        }
+        float ms = 0.f;
+        const int reps = 5;
+        hipEventRecord(e0, s);
+        for (int r = 0; r < reps && rc == DCT2D_OK; ++r) rc = launch();
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (best < 0 || ms < best_t) {
+            best = v;
+            best_t = ms;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(src);
+    hipFree(dst);
+    hipFree(ref);
+    if (rc != DCT2D_OK) return rc;
+    if (best < 0) return DCT2D_ERR_HIP;
+    if (best_ms) *best_ms = best_t;
+    return dct2d_set_variant(rows, cols, dir, precision, best);
+}
+
+const char* dct2d_status_string(int status)
+{
+    switch (status) {
+    case DCT2D_OK: return "ok";
+    case DCT2D_ERR_ARG: return "invalid argument";
+    case DCT2D_ERR_SIZE: return "unsupported array shape";
+    case DCT2D_ERR_STRIDE: return "stride smaller than rows*cols";
+    case DCT2D_ERR_ALIGN: return "pointer or stride not 16-byte aligned";
+    case DCT2D_ERR_PRECISION: return "precision not available for this shape";
+    case DCT2D_ERR_HIP: return "HIP runtime error";
+    case DCT2D_ERR_NOINIT: return "no usable device";
+    case DCT2D_ERR_NOMEM: return "out of memory";
+    default: return "unknown status";
+    }
+}
+
+const char* dct2d_version(void) { return "dct2d-mi355x 0.1.0 (gfx950)"; }
+
+} // extern "C"

@@ -1,0 +1,70 @@
+// Internal (non-exported) declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/dct2d.h"
+
+namespace dct {
+
+// Lengths with FFT twiddle sets: 8 .. 1024 (index = log2 L - 3).
+constexpr int kMinLog = 3, kMaxLog = 10, kNumLens = kMaxLog - kMinLog + 1;
+// Sizes with dense Q tables for the matrix (MFMA) paths: 8, 16, 32, 64.
+constexpr int kNumDense = 4;
+
+// Plan-owned device tables (Section 3.2: tables built once, reused by every call).
+struct DeviceTables {
+    int device = -1;
+    int num_cu = 0;
+    float2* tw = nullptr;               // twiddle bank (complex entries)
+    int tw_off[kNumLens] = {};          // offset of TwLayout<L> per length
+    // Dense Q_n for the matrix paths, row-major n x n, for n = 8 << i:
+    float* q_f32[kNumDense] = {};       // rounded to float32
+    uint16_t* q_bf16[kNumDense] = {};   // 3 planes: hi, mid, lo (bf16 bit patterns)
+    uint16_t* q_f16[kNumDense] = {};    // 2 planes: hi, lo (fp16 bit patterns)
+    uint8_t* q_f8[kNumDense] = {};      // 1 plane: fp8 e4m3 of Q * 2^kF8QShift
+    // Dense Q_n for arbitrary image axes (n <= 1024), generated on demand at plan time.
+    void* pool = nullptr;               // single allocation holding everything above
+    size_t pool_bytes = 0;
+};
+
+constexpr int kF8QShift = 8; // fp8 copy of Q is stored scaled by 2^8 (entries in the normal range)
+
+// Returns the tables of the current device, initialising them on first use.
+// Thread-safe.  nullptr on failure (status in *err).
+const DeviceTables* tables_current(int* err);
+int tables_init_device(int device);
+void tables_release_all();
+
+// Generates dense float32 Q_n (eq. 1) for an arbitrary n into a device buffer.
+int tables_dense_q(int n, float* dst, hipStream_t s);
+
+inline const float2* tw_for(const DeviceTables* t, int L)
+{
+    int lg = 0;
+    while ((1 << lg) < L) ++lg;
+    return t->tw + t->tw_off[lg - kMinLog];
+}
+
+inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// ---- kernel launchers (each returns a DCT2D_* status) ------------------------------
+struct Job {
+    int dir;           // DCT2D_FORWARD / INVERSE / ROUNDTRIP
+    const float* in;
+    float* out;
+    int64_t batch;
+    int32_t rows, cols;
+    int64_t in_stride, out_stride;
+    hipStream_t stream;
+    int variant;
+};
+
+int launch_fp32(const DeviceTables* t, const Job& j);
+int fp32_variant_count(int rows, int cols, int dir);
+
+int launch_mfma(const DeviceTables* t, const Job& j, int precision);
+int mfma_supported(int rows, int cols, int precision);
+int mfma_variant_count(int rows, int cols, int dir, int precision);
+
+} // namespace dct

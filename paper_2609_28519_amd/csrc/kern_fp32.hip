@@ -1,0 +1,331 @@
+// Float32 2D DCT kernels on the vector ALU (all sizes, the "plain FP32" path).
+//
+// Separable evaluation of eq. 2 (Section 2.1): a length-W transform along every row,
+// then a length-H transform along every column, each done by one thread on a vector
+// held in its registers (dct1d.hpp).  The paper's CPU organisation (Section 3.1,
+// Algorithm 1) copies rows into padded scratch of stride n+4, runs one pass per
+// lane, re-packs into bands and runs the other pass.  The GPU analogue here:
+//
+//   fused kernel (rows, cols <= 128): a workgroup stages a tile of whole arrays in
+//   LDS with coalesced 16-byte global loads, using a padded row pitch of cols+4
+//   floats (so 16-byte row reads of consecutive rows and 4-byte column reads of
+//   consecutive columns fall in distinct banks), then
+//     row pass:    thread (array, r) reads row r from LDS, transforms, writes back
+//     column pass: thread (array, c) reads column c, transforms, writes back
+//   and the tile leaves through coalesced 16-byte stores.  One HBM read and one HBM
+//   write per element; the fused round trip runs forward columns and inverse
+//   columns back to back in registers (Prop. 1: no intermediate correction).
+//
+//   two-pass kernels (an axis of 256): the row pass and the column pass are separate
+//   launches over HBM (each thread owns a whole row or a whole column; column
+//   accesses are coalesced across the wavefront's consecutive columns).
+#include "dct1d.hpp"
+#include "internal.hpp"
+
+namespace dct {
+namespace {
+
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+
+template <int H, int W>
+struct B2D {
+    static constexpr int TB = cmax(H, W);            // threads per array
+    static constexpr int NT = TB >= 128 ? TB : 256;  // threads per workgroup
+    static constexpr int BPW = NT / TB;              // arrays per tile
+    static constexpr int P = W + 4;                  // LDS row pitch in floats
+    static constexpr int HP = H * P;
+    // array pitch in LDS: congruent to TB mod 64 so the arrays of one wavefront start
+    // in different banks during column reads
+    static constexpr int BS = TB >= 64 ? HP : HP + ((TB - HP % 64) + 64) % 64;
+    static constexpr int CPB = H * W / 4;            // float4 chunks per array
+    static constexpr int CHUNKS = CPB * BPW;
+    static constexpr int CPT = (CHUNKS + NT - 1) / NT;
+    static constexpr int LDS_FLOATS = BPW * BS;
+};
+
+template <int L, int DIR>
+__device__ __forceinline__ void apply1d(float (&v)[L], const float2* __restrict__ tw)
+{
+    if (DIR == DCT2D_FORWARD) {
+        dct2_ortho<L>(v, tw);
+    } else if (DIR == DCT2D_INVERSE) {
+        dct3_ortho<L>(v, tw);
+    } else {
+        dct2_ortho<L>(v, tw);
+        dct3_ortho<L>(v, tw);
+    }
+}
+
+// Row pass on an LDS tile: thread (array tb, row r) transforms its row in place.
+template <int H, int W, bool INV>
+__device__ __forceinline__ void lds_row_pass(float* lds, int tb, int r, const float2* __restrict__ tw)
+{
+    using C = B2D<H, W>;
+    if (r < H) {
+        float v[W];
+        float* row = lds + tb * C::BS + r * C::P;
+#pragma unroll
+        for (int j = 0; j < W / 4; ++j) {
+            const float4 q = *reinterpret_cast<const float4*>(row + 4 * j);
+            v[4 * j] = q.x; v[4 * j + 1] = q.y; v[4 * j + 2] = q.z; v[4 * j + 3] = q.w;
+        }
+        if (INV) dct3_ortho<W>(v, tw); else dct2_ortho<W>(v, tw);
+#pragma unroll
+        for (int j = 0; j < W / 4; ++j)
+            *reinterpret_cast<float4*>(row + 4 * j) = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+    }
+}
+
+template <int H, int W, int DIR>
+__global__ void __launch_bounds__((B2D<H, W>::NT))
+k_fused(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t out_stride,
+        const float2* __restrict__ twh, const float2* __restrict__ tww)
+{
+    using C = B2D<H, W>;
+    __shared__ float4 lds4[(C::LDS_FLOATS + 3) / 4];
+    float* lds = reinterpret_cast<float*>(lds4);
+    const int t = threadIdx.x;
+    const int tb = t / C::TB, tl = t % C::TB;
+    const int64_t ntiles = (batch + C::BPW - 1) / C::BPW;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t b0 = tile * C::BPW;
+#pragma unroll
+        for (int i = 0; i < C::CPT; ++i) {
+            const int c = t + C::NT * i;
+            if (C::CHUNKS % C::NT == 0 || c < C::CHUNKS) {
+                const int b = c / C::CPB, q = c % C::CPB;
+                const int r = q / (W / 4), c4 = q % (W / 4);
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (b0 + b < batch) v = *reinterpret_cast<const float4*>(in + (b0 + b) * in_stride + 4 * q);
+                *reinterpret_cast<float4*>(lds + b * C::BS + r * C::P + 4 * c4) = v;
+            }
+        }
+        __syncthreads();
+        lds_row_pass<H, W, DIR == DCT2D_INVERSE>(lds, tb, tl, tww);
+        __syncthreads();
+        if (tl < W) {
+            float v[H];
+            float* col = lds + tb * C::BS + tl;
+#pragma unroll
+            for (int r = 0; r < H; ++r) v[r] = col[r * C::P];
+            apply1d<H, DIR>(v, twh);
+#pragma unroll
+            for (int r = 0; r < H; ++r) col[r * C::P] = v[r];
+        }
+        __syncthreads();
+        if (DIR == DCT2D_ROUNDTRIP) {
+            lds_row_pass<H, W, true>(lds, tb, tl, tww);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < C::CPT; ++i) {
+            const int c = t + C::NT * i;
+            if (C::CHUNKS % C::NT == 0 || c < C::CHUNKS) {
+                const int b = c / C::CPB, q = c % C::CPB;
+                const int r = q / (W / 4), c4 = q % (W / 4);
+                const float4 v = *reinterpret_cast<const float4*>(lds + b * C::BS + r * C::P + 4 * c4);
+                if (b0 + b < batch) *reinterpret_cast<float4*>(out + (b0 + b) * out_stride + 4 * q) = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Row pass over HBM: one thread per row of length L (rows of `rows` per array).
+template <int L, int DIR>
+__global__ void __launch_bounds__(64)
+k_rows(const float* in, float* out, int64_t batch, int32_t rows, int64_t in_stride,
+       int64_t out_stride, const float2* __restrict__ tw)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= batch * rows) return;
+    const int64_t b = g / rows;
+    const int r = (int)(g % rows);
+    const float* src = in + b * in_stride + (int64_t)r * L;
+    float* dst = out + b * out_stride + (int64_t)r * L;
+    float v[L];
+#pragma unroll
+    for (int j = 0; j < L / 4; ++j) {
+        const float4 q = *reinterpret_cast<const float4*>(src + 4 * j);
+        v[4 * j] = q.x; v[4 * j + 1] = q.y; v[4 * j + 2] = q.z; v[4 * j + 3] = q.w;
+    }
+    apply1d<L, DIR>(v, tw);
+#pragma unroll
+    for (int j = 0; j < L / 4; ++j)
+        *reinterpret_cast<float4*>(dst + 4 * j) = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+}
+
+// Column pass over HBM: one thread per column of length L; consecutive lanes take
+// consecutive columns, so every load/store instruction is contiguous across the wave.
+template <int L, int DIR>
+__global__ void __launch_bounds__(64)
+k_cols(const float* in, float* out, int64_t batch, int32_t cols, int64_t in_stride,
+       int64_t out_stride, const float2* __restrict__ tw)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= batch * cols) return;
+    const int64_t b = g / cols;
+    const int c = (int)(g % cols);
+    const float* src = in + b * in_stride + c;
+    float* dst = out + b * out_stride + c;
+    float v[L];
+#pragma unroll
+    for (int r = 0; r < L; ++r) v[r] = src[(int64_t)r * cols];
+    apply1d<L, DIR>(v, tw);
+#pragma unroll
+    for (int r = 0; r < L; ++r) dst[(int64_t)r * cols] = v[r];
+}
+
+template <int H, int W>
+int launch_fused_hw(const DeviceTables* t, const Job& j)
+{
+    using C = B2D<H, W>;
+    const int64_t ntiles = (j.batch + C::BPW - 1) / C::BPW;
+    int per_cu = 0;
+    const float2* twh = tw_for(t, H);
+    const float2* tww = tw_for(t, W);
+    hipError_t e = hipSuccess;
+    switch (j.dir) {
+    case DCT2D_FORWARD:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused<H, W, DCT2D_FORWARD>, C::NT, 0);
+        break;
+    case DCT2D_INVERSE:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused<H, W, DCT2D_INVERSE>, C::NT, 0);
+        break;
+    default:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused<H, W, DCT2D_ROUNDTRIP>, C::NT, 0);
+        break;
+    }
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    const int64_t cap = (int64_t)t->num_cu * per_cu * 4;
+    const unsigned grid = (unsigned)(ntiles < cap ? ntiles : cap);
+    switch (j.dir) {
+    case DCT2D_FORWARD:
+        k_fused<H, W, DCT2D_FORWARD><<<grid, C::NT, 0, j.stream>>>(j.in, j.out, j.batch, j.in_stride,
+                                                                   j.out_stride, twh, tww);
+        break;
+    case DCT2D_INVERSE:
+        k_fused<H, W, DCT2D_INVERSE><<<grid, C::NT, 0, j.stream>>>(j.in, j.out, j.batch, j.in_stride,
+                                                                   j.out_stride, twh, tww);
+        break;
+    default:
+        k_fused<H, W, DCT2D_ROUNDTRIP><<<grid, C::NT, 0, j.stream>>>(j.in, j.out, j.batch, j.in_stride,
+                                                                     j.out_stride, twh, tww);
+        break;
+    }
+    return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
+}
+
+template <int L, int DIR>
+void launch_rows(const DeviceTables* t, const float* in, float* out, int64_t batch, int rows,
+                 int64_t is, int64_t os, hipStream_t s)
+{
+    const int64_t n = batch * rows;
+    k_rows<L, DIR><<<(unsigned)((n + 63) / 64), 64, 0, s>>>(in, out, batch, rows, is, os, tw_for(t, L));
+}
+
+template <int L, int DIR>
+void launch_cols(const DeviceTables* t, const float* in, float* out, int64_t batch, int cols,
+                 int64_t is, int64_t os, hipStream_t s)
+{
+    const int64_t n = batch * cols;
+    k_cols<L, DIR><<<(unsigned)((n + 63) / 64), 64, 0, s>>>(in, out, batch, cols, is, os, tw_for(t, L));
+}
+
+// Row pass with length `len` (runtime) -> template dispatch.
+template <int DIR>
+int rows_any(const DeviceTables* t, int len, const float* in, float* out, int64_t batch, int rows,
+             int64_t is, int64_t os, hipStream_t s)
+{
+    switch (len) {
+    case 8: launch_rows<8, DIR>(t, in, out, batch, rows, is, os, s); break;
+    case 16: launch_rows<16, DIR>(t, in, out, batch, rows, is, os, s); break;
+    case 32: launch_rows<32, DIR>(t, in, out, batch, rows, is, os, s); break;
+    case 64: launch_rows<64, DIR>(t, in, out, batch, rows, is, os, s); break;
+    case 128: launch_rows<128, DIR>(t, in, out, batch, rows, is, os, s); break;
+    case 256: launch_rows<256, DIR>(t, in, out, batch, rows, is, os, s); break;
+    default: return DCT2D_ERR_SIZE;
+    }
+    return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
+}
+
+template <int DIR>
+int cols_any(const DeviceTables* t, int len, const float* in, float* out, int64_t batch, int cols,
+             int64_t is, int64_t os, hipStream_t s)
+{
+    switch (len) {
+    case 8: launch_cols<8, DIR>(t, in, out, batch, cols, is, os, s); break;
+    case 16: launch_cols<16, DIR>(t, in, out, batch, cols, is, os, s); break;
+    case 32: launch_cols<32, DIR>(t, in, out, batch, cols, is, os, s); break;
+    case 64: launch_cols<64, DIR>(t, in, out, batch, cols, is, os, s); break;
+    case 128: launch_cols<128, DIR>(t, in, out, batch, cols, is, os, s); break;
+    case 256: launch_cols<256, DIR>(t, in, out, batch, cols, is, os, s); break;
+    default: return DCT2D_ERR_SIZE;
+    }
+    return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
+}
+
+// Two-pass schedule over HBM (rows, then columns; the round trip needs a third pass).
+int launch_two_pass(const DeviceTables* t, const Job& j)
+{
+    int rc;
+    switch (j.dir) {
+    case DCT2D_FORWARD:
+        rc = rows_any<DCT2D_FORWARD>(t, j.cols, j.in, j.out, j.batch, j.rows, j.in_stride, j.out_stride, j.stream);
+        if (rc) return rc;
+        return cols_any<DCT2D_FORWARD>(t, j.rows, j.out, j.out, j.batch, j.cols, j.out_stride, j.out_stride, j.stream);
+    case DCT2D_INVERSE:
+        rc = rows_any<DCT2D_INVERSE>(t, j.cols, j.in, j.out, j.batch, j.rows, j.in_stride, j.out_stride, j.stream);
+        if (rc) return rc;
+        return cols_any<DCT2D_INVERSE>(t, j.rows, j.out, j.out, j.batch, j.cols, j.out_stride, j.out_stride, j.stream);
+    default:
+        rc = rows_any<DCT2D_FORWARD>(t, j.cols, j.in, j.out, j.batch, j.rows, j.in_stride, j.out_stride, j.stream);
+        if (rc) return rc;
+        rc = cols_any<DCT2D_ROUNDTRIP>(t, j.rows, j.out, j.out, j.batch, j.cols, j.out_stride, j.out_stride, j.stream);
+        if (rc) return rc;
+        return rows_any<DCT2D_INVERSE>(t, j.cols, j.out, j.out, j.batch, j.rows, j.out_stride, j.out_stride, j.stream);
+    }
+}
+
+template <int H>
+int fused_w(const DeviceTables* t, const Job& j)
+{
+    switch (j.cols) {
+    case 8: return launch_fused_hw<H, 8>(t, j);
+    case 16: return launch_fused_hw<H, 16>(t, j);
+    case 32: return launch_fused_hw<H, 32>(t, j);
+    case 64: return launch_fused_hw<H, 64>(t, j);
+    case 128: return launch_fused_hw<H, 128>(t, j);
+    default: return DCT2D_ERR_SIZE;
+    }
+}
+
+int launch_fused(const DeviceTables* t, const Job& j)
+{
+    switch (j.rows) {
+    case 8: return fused_w<8>(t, j);
+    case 16: return fused_w<16>(t, j);
+    case 32: return fused_w<32>(t, j);
+    case 64: return fused_w<64>(t, j);
+    case 128: return fused_w<128>(t, j);
+    default: return DCT2D_ERR_SIZE;
+    }
+}
+
+} // namespace
+
+// Variant 0: fused LDS kernel where both axes are <= 128, else two-pass.
+// Variant 1: two-pass (row pass then column pass over HBM), all sizes.
+int fp32_variant_count(int rows, int cols, int)
+{
+    return (rows <= 128 && cols <= 128) ? 2 : 1;
+}
+
+int launch_fp32(const DeviceTables* t, const Job& j)
+{
+    const bool fusable = j.rows <= 128 && j.cols <= 128;
+    if (fusable && j.variant == 0) return launch_fused(t, j);
+    return launch_two_pass(t, j);
+}
+
+} // namespace dct

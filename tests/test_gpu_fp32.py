@@ -1,0 +1,188 @@
+"""GPU parity of the float32 path against the FP64 oracle (Section 6 eq. 5 metric).
+
+Gates: normwise relative error per array <= 2e-6 for forward and inverse and
+<= 4e-6 for the fused round trip, whose reference is the input itself (the exact
+round trip is the identity, Section 2.1).  Inputs come from the seeded generators
+in ``workloads``; expected values come only from the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_util import GATE, assert_parity, errors, run, to_gpu
+
+pytestmark = pytest.mark.gpu
+SIZES = (8, 16, 32, 64, 128, 256)
+DIRS = ("forward", "inverse", "roundtrip")
+
+
+def _lib():
+    import paper_2609_28519_amd as dct
+    dct.init(0)
+    return dct
+
+
+@pytest.mark.parametrize("direction", DIRS)
+def test_c1_uniform8(direction):
+    """4096 blocks of 8x8 U[-1,1] (the small configuration), every block checked."""
+    _lib()
+    x = workloads.c1_uniform8().x
+    y = run(x, direction)
+    e = assert_parity(x, y, direction, label="c1")
+    assert e.max() < 5e-7  # far inside the gate: float32 error is ~1e-7 (Section 6 Table 3 band)
+
+
+def test_c1_two_call_roundtrip():
+    """The materialised round trip (forward then inverse calls) also meets the gate (Section 4.2)."""
+    _lib()
+    x = workloads.c1_uniform8().x
+    y = run(run(x, "forward"), "inverse")
+    assert_parity(x, y, "roundtrip", label="c1 two-call")
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("direction", DIRS)
+def test_square_sizes_ragged_tail(n, direction):
+    """Batches spanning several tiles plus a ragged tail, N(0,1)."""
+    _lib()
+    batch = {8: 1001, 16: 523, 32: 131, 64: 37, 128: 11, 256: 5}[n]
+    x = workloads.c3_normal(n, batch=batch, seed=1234 + n).x
+    y = run(x, direction)
+    assert_parity(x, y, direction, label="N=%d" % n)
+
+
+@pytest.mark.parametrize("h,w", [(8, 16), (16, 8), (8, 64), (64, 8), (32, 128), (128, 32), (16, 256),
+                                 (256, 8), (64, 256), (256, 128), (128, 64)])
+@pytest.mark.parametrize("direction", DIRS)
+def test_rectangles(h, w, direction):
+    """Rectangular arrays Q_h X Q_w^T (Section 7.1)."""
+    _lib()
+    g = np.random.default_rng(h * 1000 + w)
+    x = g.standard_normal((7, h, w)).astype(np.float32)
+    y = run(x, direction)
+    assert_parity(x, y, direction, label="%dx%d" % (h, w))
+
+
+@pytest.mark.parametrize("n", (8, 64, 256))
+def test_inverse_of_stored_spectrum(n):
+    """Inverse applied to fl32(C(X)) recovers X (the inverse's own input is the spectrum)."""
+    _lib()
+    x = workloads.c3_normal(n, batch=9, seed=77).x
+    spec = oracle.forward(x).astype(np.float32)
+    y = run(spec, "inverse")
+    assert_parity(spec, y, "inverse", label="spectrum N=%d" % n)
+    assert oracle.e_rel(y, x, x).max() < 4e-6
+
+
+@pytest.mark.parametrize("n", (16, 64, 256))
+def test_strided_batch_and_guards(n):
+    """stride > rows*cols: the gaps between arrays are guard values that must stay untouched."""
+    import torch
+    import paper_2609_28519_amd as dct
+    _lib()
+    batch, gap = 9, 12
+    stride = n * n + gap
+    g = np.random.default_rng(n)
+    x = g.standard_normal((batch, n, n)).astype(np.float32)
+    buf = np.full(batch * stride + 64, np.float32(1234.5), np.float32)
+    for b in range(batch):
+        buf[b * stride:b * stride + n * n] = x[b].ravel()
+    t = to_gpu(buf)
+    dct.forward_(t, rows=n, cols=n, stride=stride)
+    torch.cuda.synchronize()
+    out = t.cpu().numpy()
+    y = np.stack([out[b * stride:b * stride + n * n].reshape(n, n) for b in range(batch)])
+    assert_parity(x, y, "forward", label="strided")
+    mask = np.ones(out.size, bool)
+    for b in range(batch):
+        mask[b * stride:b * stride + n * n] = False
+    assert np.all(out[mask] == np.float32(1234.5)), "guard values overwritten"
+
+
+@pytest.mark.parametrize("n", (8, 32, 128, 256))
+def test_out_of_place_leaves_input_unchanged(n):
+    _lib()
+    x = workloads.c3_normal(n, batch=6, seed=5).x
+    t = to_gpu(x)
+    import torch
+    import paper_2609_28519_amd as dct
+    for d in DIRS:
+        out = dct.transform(t, None, d, "fp32")
+        torch.cuda.synchronize()
+        assert np.array_equal(t.cpu().numpy(), x)
+        assert_parity(x, out.cpu().numpy(), d, label="oop")
+
+
+def test_zero_and_extreme_blocks():
+    """Zero blocks give exact zeros (absolute check); 2^+-100 and 1e30 blocks meet the gate."""
+    _lib()
+    g = np.random.default_rng(3)
+    for n in SIZES:
+        x = g.uniform(-1, 1, (6, n, n))
+        x[0] = 0.0
+        x[1] *= 2.0 ** 100
+        x[2] *= 2.0 ** -100
+        x[3] *= 1e30
+        x = x.astype(np.float32)
+        for d in DIRS:
+            y = run(x, d)
+            assert np.all(y[0] == 0.0)
+            assert_parity(x, y, d, label="extreme N=%d" % n)
+
+
+def test_batch_zero_and_one():
+    import torch
+    import paper_2609_28519_amd as dct
+    _lib()
+    t = torch.zeros((0, 16, 16), device="cuda")
+    dct.forward_(t)
+    x = workloads.c3_normal(32, batch=1, seed=9).x
+    assert_parity(x, run(x, "forward"), "forward")
+
+
+def test_determinism_bitwise():
+    """The same call on the same input gives bitwise-identical output."""
+    _lib()
+    for n in (8, 64, 256):
+        x = workloads.c3_normal(n, batch=33, seed=n).x
+        a = run(x, "roundtrip")
+        b = run(x, "roundtrip")
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("direction", DIRS)
+def test_c2_mixture_fp32(direction):
+    """65536 16x16 tiles of the mixed configuration on the float32 path, per category."""
+    _lib()
+    bt = workloads.c2_mixture16()
+    y = run(bt.x, direction)
+    e = errors(bt.x, y, direction)
+    for c in np.unique(bt.category):
+        assert e[bt.category == c].max() <= GATE[direction], "category %d" % c
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_full_size_c3_sampled(n):
+    """Full 512 MiB batch (2^27/N^2 arrays of N(0,1)), in place, in the launch configuration the
+    benchmark times; 192 sampled arrays (first, last, random) checked against the oracle."""
+    import torch
+    import paper_2609_28519_amd as dct
+    _lib()
+    bt = workloads.c3_normal(n)
+    batch = bt.x.shape[0]
+    g = np.random.default_rng(n)
+    idx = np.unique(np.concatenate([[0, batch - 1], g.integers(0, batch, 190)]))
+    xs = bt.x[idx].copy()
+    t = to_gpu(bt.x)
+    del bt
+    dct.forward_(t)
+    torch.cuda.synchronize()
+    y = t[torch.from_numpy(idx).cuda()].cpu().numpy()
+    assert_parity(xs, y, "forward", label="full N=%d" % n)
+    dct.inverse_(t)
+    torch.cuda.synchronize()
+    y2 = t[torch.from_numpy(idx).cuda()].cpu().numpy()
+    assert oracle.e_rel(y2, xs, xs).max() <= GATE["roundtrip"]
+    del t
+    torch.cuda.empty_cache()
