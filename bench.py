@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--cpu-frac", type=float, default=0.25, help="fraction of each batch the oracle runs on")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--log2-floats", type=int, default=27, help="floats per size (default 2^27 = 512 MiB)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the (untimed) autotuning pass")
     return ap.parse_args()
 
 
@@ -72,6 +73,17 @@ def main():
         bufs[n] = torch.from_numpy(x).to(dev)
         print("input N=%d batch=%d (%.0f MiB)" % (n, batch, x.nbytes / 2 ** 20), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+
+    # ---- autotune (untimed, on the library's own scratch data, before any measurement) --
+    tuned = {}
+    if not args.no_tune:
+        for n in sizes:
+            for d in DIRS:
+                for p in ("fp32",):
+                    if dct.variant_count(n, n, d, p) > 1:
+                        dct.tune(n, n, d, p, batch=(1 << 26) // (n * n), stream=stream)
+                    tuned["%d/%s/%s" % (n, d, p)] = dct.get_variant(n, n, d, p)
+        torch.cuda.synchronize()
 
     def call(n, d, prec, t):
         return dct.transform(t, t, d, prec, stream=stream)
@@ -171,7 +183,7 @@ def main():
                                   "forward + inverse + fused round trip, in place" % (args.log2_floats,
                                                                                      args.log2_floats),
                       "sizes": sizes, "batch": {str(n): int(host[n].shape[0]) for n in sizes},
-                      "precision": args.precision},
+                      "precision": args.precision, "variants": tuned},
            "hbm_frac": round(value / HBM_PEAK_GBS, 4), "wall_s": round(wall, 3),
            "roofline": roofline, "per_size": per, "compare_forward_GBps": compare}
 

@@ -27,6 +27,16 @@ namespace {
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
+// Returns p unchanged but opaque to the optimiser.  Used once per tile iteration so the
+// twiddle loads (scalar, cache-resident) are re-issued inside the loop instead of being
+// hoisted out of it, which would pin ~L twiddles in scalar registers for the whole
+// kernel and spill them.
+__device__ __forceinline__ twptr per_iteration(const float2* p)
+{
+    asm volatile("" : "+s"(p));
+    return (twptr)p;
+}
+
 template <int H, int W>
 struct B2D {
     static constexpr int TB = cmax(H, W);            // threads per array
@@ -44,7 +54,7 @@ struct B2D {
 };
 
 template <int L, int DIR>
-__device__ __forceinline__ void apply1d(float (&v)[L], const float2* __restrict__ tw)
+__device__ __forceinline__ void apply1d(float (&v)[L], twptr tw)
 {
     if (DIR == DCT2D_FORWARD) {
         dct2_ortho<L>(v, tw);
@@ -52,13 +62,16 @@ __device__ __forceinline__ void apply1d(float (&v)[L], const float2* __restrict_
         dct3_ortho<L>(v, tw);
     } else {
         dct2_ortho<L>(v, tw);
+        // re-read the (identical) twiddles for the inverse instead of keeping the
+        // forward's values live in scalar registers across both transforms
+        asm volatile("" : "+s"(tw));
         dct3_ortho<L>(v, tw);
     }
 }
 
 // Row pass on an LDS tile: thread (array tb, row r) transforms its row in place.
 template <int H, int W, bool INV>
-__device__ __forceinline__ void lds_row_pass(float* lds, int tb, int r, const float2* __restrict__ tw)
+__device__ __forceinline__ void lds_row_pass(float* lds, int tb, int r, twptr tw)
 {
     using C = B2D<H, W>;
     if (r < H) {
@@ -79,7 +92,7 @@ __device__ __forceinline__ void lds_row_pass(float* lds, int tb, int r, const fl
 template <int H, int W, int DIR>
 __global__ void __launch_bounds__((B2D<H, W>::NT))
 k_fused(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t out_stride,
-        const float2* __restrict__ twh, const float2* __restrict__ tww)
+        const float2* __restrict__ twh_in, const float2* __restrict__ tww_in)
 {
     using C = B2D<H, W>;
     __shared__ float4 lds4[(C::LDS_FLOATS + 3) / 4];
@@ -88,6 +101,8 @@ k_fused(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t o
     const int tb = t / C::TB, tl = t % C::TB;
     const int64_t ntiles = (batch + C::BPW - 1) / C::BPW;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const twptr twh = per_iteration(twh_in);
+        const twptr tww = per_iteration(tww_in);
         const int64_t b0 = tile * C::BPW;
 #pragma unroll
         for (int i = 0; i < C::CPT; ++i) {
@@ -131,12 +146,108 @@ k_fused(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t o
     }
 }
 
+// Wave-local fused kernel (one wavefront per workgroup, rows and cols <= 64): each
+// lane loads its row straight from HBM into registers (the lanes of a wavefront cover
+// 64/TB consecutive arrays, so the wavefront reads one contiguous span), transforms
+// it, and writes it into a padded LDS tile; after a wavefront-local barrier each lane
+// reads one column, transforms it and stores it directly (consecutive lanes hold
+// consecutive columns).  The round trip goes back through LDS for the inverse row
+// pass and leaves with 16-byte row stores.  Only the row-to-column re-layout uses
+// LDS, and no barrier couples different wavefronts.
+template <int H, int W>
+struct WaveCfg {
+    static constexpr int TB = cmax(H, W);
+    static_assert(TB <= 64, "one wavefront per tile");
+    static constexpr int BPW = 64 / TB;
+    static constexpr int P = W + 4;
+    static constexpr int HP = H * P;
+    static constexpr int BS = TB >= 64 ? HP : HP + ((TB - HP % 64) + 64) % 64;
+    static constexpr int LDS_FLOATS = BPW * BS;
+};
+
+template <int H, int W, int DIR>
+__global__ void __launch_bounds__(64)
+k_wave(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t out_stride,
+       const float2* __restrict__ twh_in, const float2* __restrict__ tww_in)
+{
+    using C = WaveCfg<H, W>;
+    __shared__ float4 lds4[(C::LDS_FLOATS + 3) / 4];
+    float* lds = reinterpret_cast<float*>(lds4);
+    const int t = threadIdx.x;
+    const int tb = t / C::TB, tl = t % C::TB;
+    const int64_t ntiles = (batch + C::BPW - 1) / C::BPW;
+    float* tile_lds = lds + tb * C::BS;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const twptr twh = per_iteration(twh_in);
+        const twptr tww = per_iteration(tww_in);
+        const int64_t b = tile * C::BPW + tb;
+        const bool valid = b < batch;
+        if (tl < H) {
+            float v[W];
+            if (valid) {
+                const float* src = in + b * in_stride + (int64_t)tl * W;
+#pragma unroll
+                for (int j = 0; j < W / 4; ++j) {
+                    const float4 q = *reinterpret_cast<const float4*>(src + 4 * j);
+                    v[4 * j] = q.x; v[4 * j + 1] = q.y; v[4 * j + 2] = q.z; v[4 * j + 3] = q.w;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < W; ++j) v[j] = 0.f;
+            }
+            if (DIR == DCT2D_INVERSE) dct3_ortho<W>(v, tww); else dct2_ortho<W>(v, tww);
+            float* row = tile_lds + tl * C::P;
+#pragma unroll
+            for (int j = 0; j < W / 4; ++j)
+                *reinterpret_cast<float4*>(row + 4 * j) = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+        }
+        __syncthreads();
+        if (tl < W) {
+            float v[H];
+            float* col = tile_lds + tl;
+#pragma unroll
+            for (int r = 0; r < H; ++r) v[r] = col[r * C::P];
+            apply1d<H, DIR>(v, twh);
+            if (DIR == DCT2D_ROUNDTRIP) {
+#pragma unroll
+                for (int r = 0; r < H; ++r) col[r * C::P] = v[r];
+            } else if (valid) {
+                float* dst = out + b * out_stride + tl;
+#pragma unroll
+                for (int r = 0; r < H; ++r) dst[(int64_t)r * W] = v[r];
+            }
+        }
+        if (DIR == DCT2D_ROUNDTRIP) {
+            __syncthreads();
+            if (tl < H) {
+                float v[W];
+                const float* row = tile_lds + tl * C::P;
+#pragma unroll
+                for (int j = 0; j < W / 4; ++j) {
+                    const float4 q = *reinterpret_cast<const float4*>(row + 4 * j);
+                    v[4 * j] = q.x; v[4 * j + 1] = q.y; v[4 * j + 2] = q.z; v[4 * j + 3] = q.w;
+                }
+                dct3_ortho<W>(v, tww);
+                if (valid) {
+                    float* dst = out + b * out_stride + (int64_t)tl * W;
+#pragma unroll
+                    for (int j = 0; j < W / 4; ++j)
+                        *reinterpret_cast<float4*>(dst + 4 * j) =
+                            make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Row pass over HBM: one thread per row of length L (rows of `rows` per array).
 template <int L, int DIR>
 __global__ void __launch_bounds__(64)
 k_rows(const float* in, float* out, int64_t batch, int32_t rows, int64_t in_stride,
-       int64_t out_stride, const float2* __restrict__ tw)
+       int64_t out_stride, const float2* __restrict__ tw_in)
 {
+    const twptr tw = (twptr)tw_in;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= batch * rows) return;
     const int64_t b = g / rows;
@@ -160,8 +271,9 @@ k_rows(const float* in, float* out, int64_t batch, int32_t rows, int64_t in_stri
 template <int L, int DIR>
 __global__ void __launch_bounds__(64)
 k_cols(const float* in, float* out, int64_t batch, int32_t cols, int64_t in_stride,
-       int64_t out_stride, const float2* __restrict__ tw)
+       int64_t out_stride, const float2* __restrict__ tw_in)
 {
+    const twptr tw = (twptr)tw_in;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= batch * cols) return;
     const int64_t b = g / cols;
@@ -214,6 +326,54 @@ int launch_fused_hw(const DeviceTables* t, const Job& j)
         break;
     }
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
+}
+
+template <int H, int W, int DIR>
+int launch_wave_dir(const DeviceTables* t, const Job& j)
+{
+    using C = WaveCfg<H, W>;
+    const int64_t ntiles = (j.batch + C::BPW - 1) / C::BPW;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wave<H, W, DIR>, 64, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int64_t cap = (int64_t)t->num_cu * per_cu * 4;
+    const unsigned grid = (unsigned)(ntiles < cap ? ntiles : cap);
+    k_wave<H, W, DIR><<<grid, 64, 0, j.stream>>>(j.in, j.out, j.batch, j.in_stride, j.out_stride, tw_for(t, H),
+                                                  tw_for(t, W));
+    return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
+}
+
+template <int H, int W>
+int launch_wave_hw(const DeviceTables* t, const Job& j)
+{
+    switch (j.dir) {
+    case DCT2D_FORWARD: return launch_wave_dir<H, W, DCT2D_FORWARD>(t, j);
+    case DCT2D_INVERSE: return launch_wave_dir<H, W, DCT2D_INVERSE>(t, j);
+    default: return launch_wave_dir<H, W, DCT2D_ROUNDTRIP>(t, j);
+    }
+}
+
+template <int H>
+int wave_w(const DeviceTables* t, const Job& j)
+{
+    switch (j.cols) {
+    case 8: return launch_wave_hw<H, 8>(t, j);
+    case 16: return launch_wave_hw<H, 16>(t, j);
+    case 32: return launch_wave_hw<H, 32>(t, j);
+    case 64: return launch_wave_hw<H, 64>(t, j);
+    default: return DCT2D_ERR_SIZE;
+    }
+}
+
+int launch_wave(const DeviceTables* t, const Job& j)
+{
+    switch (j.rows) {
+    case 8: return wave_w<8>(t, j);
+    case 16: return wave_w<16>(t, j);
+    case 32: return wave_w<32>(t, j);
+    case 64: return wave_w<64>(t, j);
+    default: return DCT2D_ERR_SIZE;
+    }
 }
 
 template <int L, int DIR>
@@ -314,17 +474,25 @@ int launch_fused(const DeviceTables* t, const Job& j)
 
 } // namespace
 
-// Variant 0: fused LDS kernel where both axes are <= 128, else two-pass.
-// Variant 1: two-pass (row pass then column pass over HBM), all sizes.
+// Variants (frozen per size by the policy table / autotuner):
+//   both axes <= 64:  0 wave-local fused, 1 LDS-staged fused, 2 two-pass
+//   an axis of 128:   0 LDS-staged fused, 1 two-pass
+//   an axis of 256:   0 two-pass
 int fp32_variant_count(int rows, int cols, int)
 {
-    return (rows <= 128 && cols <= 128) ? 2 : 1;
+    if (rows <= 64 && cols <= 64) return 3;
+    if (rows <= 128 && cols <= 128) return 2;
+    return 1;
 }
 
 int launch_fp32(const DeviceTables* t, const Job& j)
 {
-    const bool fusable = j.rows <= 128 && j.cols <= 128;
-    if (fusable && j.variant == 0) return launch_fused(t, j);
+    if (j.rows <= 64 && j.cols <= 64) {
+        if (j.variant == 0) return launch_wave(t, j);
+        if (j.variant == 1) return launch_fused(t, j);
+        return launch_two_pass(t, j);
+    }
+    if (j.rows <= 128 && j.cols <= 128 && j.variant == 0) return launch_fused(t, j);
     return launch_two_pass(t, j);
 }
 

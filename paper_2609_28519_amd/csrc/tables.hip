@@ -1,10 +1,10 @@
 // Plan-owned device tables, generated on the GPU in FP64 (the only FP64 work on the
 // device) and rounded once to the formats the kernels read.
 //
-//  * FFT / DCT twiddles for every power-of-two length 8..1024, laid out as
-//    TwLayout<L> (dct1d.hpp): W_M^j, W_L^k, a_k W_4L^k and W_4L^-k / (a_k L), where
-//    a_k are the normalisation factors of eq. 1 (Section 2.1) folded into the first
-//    and last twiddles (Section 2.2, Prop. 1: scales folded into stores).
+//  * FFT / DCT-IV twiddles for every power-of-two length 8..1024, laid out as
+//    TwLayout<L> (dct1d.hpp), with the normalisation factors a_k of eq. 1
+//    (Section 2.1) folded into the DCT-IV post-twiddles and the length-2 base case
+//    (Section 2.2, Prop. 1: scales folded into the stores).
 //  * Dense Q_n of eq. 1 for n = 8, 16, 32, 64 (the matrix paths) in float32, split
 //    into three bf16 planes (hi, mid, lo), two fp16 planes (hi, lo), and one fp8
 //    e4m3 plane of Q * 2^8.  Each split plane is the round-to-nearest-even of what
@@ -78,31 +78,35 @@ __device__ uint8_t f8e4m3_bits(double r)
     return (uint8_t)(s | ((ex + 7) << 3) | mant);
 }
 
+// Twiddle table of one top length L, layout TwLayout<L> (dct1d.hpp).
 __global__ void k_twiddles(float2* out, int L)
 {
-    const int M = L / 2;
-    const int FFT = 0, COMB = M / 2, POST = COMB + M / 2 + 1, PRE = POST + M + 1, SIZE = PRE + M + 1;
+    const int F = L / 8 > 1 ? L / 8 : 1, TOP = L / 4, SIZE = F + L - 1;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= SIZE) return;
     double s, c;
-    if (i < COMB) { // W_M^j = exp(-2 pi i j / M)
-        const int j = i - FFT;
-        sincospi(2.0 * j / M, &s, &c);
+    if (i < F) { // W_{L/4}^e
+        sincospi(2.0 * i / TOP, &s, &c);
         out[i] = make_float2((float)c, (float)-s);
-    } else if (i < POST) { // W_L^k
-        const int k = i - COMB;
-        sincospi(2.0 * k / L, &s, &c);
+        return;
+    }
+    if (i == F + L - 2) { // base: length-2 DCT-II scales sqrt(1/L) (= sqrt(2/L) cos(pi/4))
+        const double b = sqrt(1.0 / L);
+        out[i] = make_float2((float)b, (float)b);
+        return;
+    }
+    // level with DCT-IV length M: entries [F + L - 2M, F + L - M)
+    int M = L / 2;
+    while (i >= F + L - M) M /= 2;
+    const int j = i - (F + L - 2 * M);
+    if (j < M / 2) { // pre: exp(-i pi (4n+1)/(4M))
+        sincospi((4.0 * j + 1.0) / (4.0 * M), &s, &c);
         out[i] = make_float2((float)c, (float)-s);
-    } else if (i < PRE) { // a_k W_4L^k
-        const int k = i - POST;
-        const double a = k == 0 ? sqrt(1.0 / L) : sqrt(2.0 / L);
-        sincospi((double)k / (2.0 * L), &s, &c);
-        out[i] = make_float2((float)(a * c), (float)(-a * s));
-    } else { // W_4L^-k / (a_k L)
-        const int k = i - PRE;
-        const double a = k == 0 ? sqrt(1.0 / L) : sqrt(2.0 / L);
-        sincospi((double)k / (2.0 * L), &s, &c);
-        out[i] = make_float2((float)(c / (a * L)), (float)(s / (a * L)));
+    } else { // post, stored conjugated: sqrt(2/L) exp(+i pi k/M)
+        const int k = j - M / 2;
+        const double a = sqrt(2.0 / L);
+        sincospi((double)k / M, &s, &c);
+        out[i] = make_float2((float)(a * c), (float)(a * s));
     }
 }
 
@@ -172,9 +176,9 @@ int tables_init_device(int device)
     size_t off = 0;
     size_t tw_entries = 0;
     for (int i = 0; i < kNumLens; ++i) {
-        const int L = 1 << (i + kMinLog), M = L / 2;
+        const int L = 1 << (i + kMinLog);
         t->tw_off[i] = (int)tw_entries;
-        tw_entries += (size_t)(3 * M + 3);
+        tw_entries += (size_t)((L / 8 > 1 ? L / 8 : 1) + L - 1);
     }
     const size_t tw_bytes = align_up(tw_entries * sizeof(float2), 256);
     off += tw_bytes;
@@ -197,8 +201,8 @@ int tables_init_device(int device)
     char* base = static_cast<char*>(pool);
     t->tw = reinterpret_cast<float2*>(base);
     for (int i = 0; i < kNumLens; ++i) {
-        const int L = 1 << (i + kMinLog), M = L / 2;
-        const int size = 3 * M + 3;
+        const int L = 1 << (i + kMinLog);
+        const int size = (L / 8 > 1 ? L / 8 : 1) + L - 1;
         k_twiddles<<<(size + 255) / 256, 256>>>(t->tw + t->tw_off[i], L);
     }
     for (int i = 0; i < kNumDense; ++i) {

@@ -186,3 +186,22 @@ def test_full_size_c3_sampled(n):
     assert oracle.e_rel(y2, xs, xs).max() <= GATE["roundtrip"]
     del t
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("h,w", [(8, 8), (16, 16), (32, 32), (64, 64), (128, 128), (256, 256), (8, 64), (64, 16),
+                                 (128, 32), (256, 64)])
+@pytest.mark.parametrize("direction", DIRS)
+def test_every_variant(h, w, direction):
+    """Every kernel variant the autotuner may pick meets the gate (the policy only changes speed)."""
+    dct = _lib()
+    g = np.random.default_rng(h + 3 * w)
+    x = g.standard_normal(((2048 // h) + 3, h, w)).astype(np.float32)
+    nv = dct.variant_count(h, w, direction, "fp32")
+    assert nv >= 1
+    keep = dct.get_variant(h, w, direction, "fp32")
+    try:
+        for v in range(nv):
+            dct.set_variant(h, w, direction, "fp32", v)
+            assert_parity(x, run(x, direction), direction, label="%dx%d v%d" % (h, w, v))
+    finally:
+        dct.set_variant(h, w, direction, "fp32", keep)
