@@ -129,18 +129,26 @@ int dct2d_transform_ex(int dir, const float* in, float* out, int64_t batch, int3
 /* ---- ragged batches: many arrays of different shapes in one launch ------------------
  * A descriptor names one array inside a caller buffer: its first element is at
  * base + offset (floats), its shape rows x cols (pitch = cols).  Arrays must not
- * overlap.  Square blocks 8..256 (powers of two) and whole images with each axis in
- * [8, 1024] are accepted.
+ * overlap.  Accepted shapes: both axes in [8, 1024] with cols a multiple of 4; shapes
+ * with both axes powers of two <= 256 use the fast kernels of the basic calls, any
+ * other shape (whole images such as 1024 x 1024 or 512 x 384) is computed with dense
+ * float32 Q_n tables (exact for non-power-of-two axes; no zero-padding).
  *
- * dct2d_ragged_plan_create copies the (host) descriptor array, sorts the items into
- * size classes, uploads the work lists to the device, picks a kernel configuration
- * per class from the autotuner's frozen table, and records the whole batch as one
- * HIP graph.  It allocates device memory (once, here).  `dir` is a DCT2D_* direction,
- * `precision` a dct2d_precision (float32-accurate paths only).
+ * dct2d_ragged_plan_create copies the (host) descriptor array, groups the items into
+ * shape classes, uploads the per-class offset lists to the device, picks each class's
+ * kernel configuration from the frozen per-size policy (the autotuner's table), and
+ * records the whole batch as one HIP graph with one concurrent branch per class.  It
+ * allocates device memory (once, here: offset lists, dense tables, the image
+ * workspace).  `dir` is a DCT2D_* direction; `precision` DCT2D_FP32, DCT2D_AUTO or a
+ * float32-accurate split path (DCT2D_SPLIT_BF16X6 / DCT2D_SPLIT_FP16X3, used for the
+ * classes that have it).  Errors: DCT2D_ERR_SIZE (shape), DCT2D_ERR_ALIGN (offset not a
+ * multiple of 4), DCT2D_ERR_ARG (overlap, empty, more than 65535 images of one shape).
  *
- * dct2d_ragged_execute runs the plan on the arrays at `base` (device pointer, 16-byte
- * aligned) with one hipGraphLaunch on `stream`, in place.  Offsets must be multiples
- * of 4.  It allocates nothing.
+ * dct2d_ragged_execute runs the plan in place on the arrays at `base` (device pointer,
+ * 16-byte aligned) with one hipGraphLaunch on `stream`.  The graph reads the base from
+ * a plan-owned device slot; when `base` differs from the previous call an 8-byte copy
+ * on `stream` updates the slot first.  It allocates nothing.  Executions of one plan on
+ * different streams must not overlap.
  */
 typedef struct {
     int64_t offset;  /* element offset from base (multiple of 4) */
@@ -155,7 +163,7 @@ int dct2d_ragged_plan_create(const dct2d_block* blocks, int64_t count, int dir, 
 int dct2d_ragged_execute(dct2d_ragged_plan* plan, float* base, void* stream);
 void dct2d_ragged_plan_destroy(dct2d_ragged_plan* plan);
 
-/* Number of kernel launches recorded in the plan's graph (diagnostics). */
+/* Items, shape classes and nodes of the plan's recorded graph (diagnostics). */
 int dct2d_ragged_plan_info(const dct2d_ragged_plan* plan, int64_t* items, int32_t* classes,
                            int32_t* graph_nodes);
 

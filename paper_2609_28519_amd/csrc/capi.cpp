@@ -104,12 +104,8 @@ int run(int dir, const float* in, float* out, int64_t batch, int32_t rows, int32
     if (rc != DCT2D_OK || batch == 0) return rc;
     const DeviceTables* t = tables_current(&rc);
     if (!t) return rc;
-    const int p = resolve_precision(rows, cols, dir, prec);
-    Job j{dir, in, out, batch, rows, cols, in_stride, out_stride, static_cast<hipStream_t>(stream),
-          variant_for(rows, cols, dir, p)};
-    if (p == DCT2D_FP32) return launch_fp32(t, j);
-    if (!mfma_supported(rows, cols, p)) return DCT2D_ERR_PRECISION;
-    return launch_mfma(t, j, p);
+    Job j{dir, in, out, batch, rows, cols, in_stride, out_stride, static_cast<hipStream_t>(stream), 0};
+    return dispatch(t, j, prec);
 }
 
 int variant_count(int rows, int cols, int dir, int prec)
@@ -134,6 +130,15 @@ __global__ void k_fill(float* p, int64_t n, uint32_t seed)
 }
 
 } // namespace
+
+int dct::dispatch(const DeviceTables* t, Job j, int prec)
+{
+    const int p = resolve_precision(j.rows, j.cols, j.dir, prec);
+    j.variant = variant_for(j.rows, j.cols, j.dir, p);
+    if (p == DCT2D_FP32) return launch_fp32(t, j);
+    if (!mfma_supported(j.rows, j.cols, p)) return DCT2D_ERR_PRECISION;
+    return launch_mfma(t, j, p);
+}
 
 extern "C" {
 
@@ -178,14 +183,25 @@ int dct2d_variant_count(int32_t rows, int32_t cols, int dir, int precision)
 int dct2d_get_variant(int32_t rows, int32_t cols, int dir, int precision)
 {
     if (!basic_size_ok(rows, cols)) return DCT2D_ERR_SIZE;
-    if (dir < 0 || dir > 2 || precision < 0 || precision >= DCT2D_AUTO) return DCT2D_ERR_ARG;
+    if (dir < 0 || dir > 2 || precision < 0 || precision > DCT2D_AUTO) return DCT2D_ERR_ARG;
+    // for DCT2D_AUTO the "variant" is the frozen path (a dct2d_precision value)
+    if (precision == DCT2D_AUTO) return resolve_precision(rows, cols, dir, DCT2D_AUTO);
     return variant_for(rows, cols, dir, precision);
 }
 
 int dct2d_set_variant(int32_t rows, int32_t cols, int dir, int precision, int variant)
 {
     if (!basic_size_ok(rows, cols)) return DCT2D_ERR_SIZE;
-    if (dir < 0 || dir > 2 || precision < 0 || precision >= DCT2D_AUTO) return DCT2D_ERR_ARG;
+    if (dir < 0 || dir > 2 || precision < 0 || precision > DCT2D_AUTO) return DCT2D_ERR_ARG;
+    if (precision == DCT2D_AUTO) {
+        // freeze the float32-accurate path used by DCT2D_AUTO
+        if (variant != DCT2D_FP32 && variant != DCT2D_SPLIT_BF16X6 && variant != DCT2D_SPLIT_FP16X3)
+            return DCT2D_ERR_ARG;
+        if (variant != DCT2D_FP32 && !mfma_supported(rows, cols, variant)) return DCT2D_ERR_PRECISION;
+        std::call_once(g_auto_once, auto_init);
+        g_auto_path[lg2(rows) - 3][lg2(cols) - 3][dir].store(variant);
+        return DCT2D_OK;
+    }
     if (variant < 0 || variant >= variant_count(rows, cols, dir, precision)) return DCT2D_ERR_ARG;
     std::lock_guard<std::mutex> lk(g_policy_mu);
     policy_init_locked();
@@ -196,7 +212,27 @@ int dct2d_set_variant(int32_t rows, int32_t cols, int dir, int precision, int va
 int dct2d_tune(int32_t rows, int32_t cols, int dir, int precision, int64_t batch, void* stream, float* best_ms)
 {
     if (!basic_size_ok(rows, cols)) return DCT2D_ERR_SIZE;
-    if (dir < 0 || dir > 2 || precision < 0 || precision >= DCT2D_AUTO || batch <= 0) return DCT2D_ERR_ARG;
+    if (dir < 0 || dir > 2 || precision < 0 || precision > DCT2D_AUTO || batch <= 0) return DCT2D_ERR_ARG;
+    if (precision == DCT2D_AUTO) {
+        // tune every float32-accurate path, then freeze the fastest one for DCT2D_AUTO
+        int best_p = -1;
+        float best = 0.f;
+        for (int p : {DCT2D_FP32, DCT2D_SPLIT_BF16X6, DCT2D_SPLIT_FP16X3}) {
+            if (variant_count(rows, cols, dir, p) <= 0) continue;
+            float ms = 0.f;
+            const int rc = dct2d_tune(rows, cols, dir, p, batch, stream, &ms);
+            if (rc != DCT2D_OK) return rc;
+            if (best_p < 0 || ms < best) {
+                best_p = p;
+                best = ms;
+            }
+        }
+        if (best_p < 0) return DCT2D_ERR_PRECISION;
+        std::call_once(g_auto_once, auto_init);
+        g_auto_path[lg2(rows) - 3][lg2(cols) - 3][dir].store(best_p);
+        if (best_ms) *best_ms = best;
+        return DCT2D_OK;
+    }
     const int nv = variant_count(rows, cols, dir, precision);
     if (nv <= 0) return DCT2D_ERR_PRECISION;
     int rc = DCT2D_OK;

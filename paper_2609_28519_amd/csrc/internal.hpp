@@ -48,6 +48,31 @@ inline const float2* tw_for(const DeviceTables* t, int L)
 
 inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// ---- array addressing ---------------------------------------------------------------
+// Array b of a batch starts at in + in_idx[b] (indexed: ragged batches) or at
+// in + b * in_stride (strided batches); likewise for the output.  When a slot is
+// given, the base pointer is read from device memory at run time instead (ragged
+// plans recorded once as a graph and replayed on any base).
+struct Addr {
+    const float* in;
+    float* out;
+    int64_t in_stride, out_stride;
+    const int64_t* in_idx;  // nullptr: strided
+    const int64_t* out_idx; // nullptr: strided
+    float* const* in_slot;  // nullptr: base = in
+    float* const* out_slot; // nullptr: base = out
+    __device__ __forceinline__ const float* src(int64_t b) const
+    {
+        const float* base = in_slot ? *in_slot : in;
+        return base + (in_idx ? in_idx[b] : b * in_stride);
+    }
+    __device__ __forceinline__ float* dst(int64_t b) const
+    {
+        float* base = out_slot ? *out_slot : out;
+        return base + (out_idx ? out_idx[b] : b * out_stride);
+    }
+};
+
 // ---- kernel launchers (each returns a DCT2D_* status) ------------------------------
 struct Job {
     int dir;           // DCT2D_FORWARD / INVERSE / ROUNDTRIP
@@ -58,7 +83,21 @@ struct Job {
     int64_t in_stride, out_stride;
     hipStream_t stream;
     int variant;
+    const int64_t* in_idx = nullptr;  // optional offset lists (ragged batches)
+    const int64_t* out_idx = nullptr;
+    float* const* in_slot = nullptr;  // optional device-resident base pointers
+    float* const* out_slot = nullptr;
+    Addr addr() const { return Addr{in, out, in_stride, out_stride, in_idx, out_idx, in_slot, out_slot}; }
 };
+
+// Resolves the precision (DCT2D_AUTO -> the frozen per-size choice) and the frozen
+// kernel variant, then launches.  Shared by the basic calls and ragged plans.
+int dispatch(const DeviceTables* t, Job j, int precision);
+
+// Dense axis pass (kern_dense.hip): one length-L transform along the columns
+// (column_pass) or rows of `count` row-major images, through a dense float32 Q_L.
+int launch_dense_axis(const Addr& a, int64_t count, int rows, int cols, bool column_pass, bool inverse,
+                      const float* q, hipStream_t s);
 
 int launch_fp32(const DeviceTables* t, const Job& j);
 int fp32_variant_count(int rows, int cols, int dir);

@@ -91,8 +91,7 @@ __device__ __forceinline__ void lds_row_pass(float* lds, int tb, int r, twptr tw
 
 template <int H, int W, int DIR>
 __global__ void __launch_bounds__((B2D<H, W>::NT))
-k_fused(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t out_stride,
-        const float2* __restrict__ twh_in, const float2* __restrict__ tww_in)
+k_fused(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* __restrict__ tww_in)
 {
     using C = B2D<H, W>;
     __shared__ float4 lds4[(C::LDS_FLOATS + 3) / 4];
@@ -111,7 +110,7 @@ k_fused(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t o
                 const int b = c / C::CPB, q = c % C::CPB;
                 const int r = q / (W / 4), c4 = q % (W / 4);
                 float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (b0 + b < batch) v = *reinterpret_cast<const float4*>(in + (b0 + b) * in_stride + 4 * q);
+                if (b0 + b < batch) v = *reinterpret_cast<const float4*>(a.src(b0 + b) + 4 * q);
                 *reinterpret_cast<float4*>(lds + b * C::BS + r * C::P + 4 * c4) = v;
             }
         }
@@ -139,7 +138,7 @@ k_fused(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t o
                 const int b = c / C::CPB, q = c % C::CPB;
                 const int r = q / (W / 4), c4 = q % (W / 4);
                 const float4 v = *reinterpret_cast<const float4*>(lds + b * C::BS + r * C::P + 4 * c4);
-                if (b0 + b < batch) *reinterpret_cast<float4*>(out + (b0 + b) * out_stride + 4 * q) = v;
+                if (b0 + b < batch) *reinterpret_cast<float4*>(a.dst(b0 + b) + 4 * q) = v;
             }
         }
         __syncthreads();
@@ -167,8 +166,7 @@ struct WaveCfg {
 
 template <int H, int W, int DIR>
 __global__ void __launch_bounds__(64)
-k_wave(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t out_stride,
-       const float2* __restrict__ twh_in, const float2* __restrict__ tww_in)
+k_wave(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* __restrict__ tww_in)
 {
     using C = WaveCfg<H, W>;
     __shared__ float4 lds4[(C::LDS_FLOATS + 3) / 4];
@@ -185,7 +183,7 @@ k_wave(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t ou
         if (tl < H) {
             float v[W];
             if (valid) {
-                const float* src = in + b * in_stride + (int64_t)tl * W;
+                const float* src = a.src(b) + (int64_t)tl * W;
 #pragma unroll
                 for (int j = 0; j < W / 4; ++j) {
                     const float4 q = *reinterpret_cast<const float4*>(src + 4 * j);
@@ -212,7 +210,7 @@ k_wave(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t ou
 #pragma unroll
                 for (int r = 0; r < H; ++r) col[r * C::P] = v[r];
             } else if (valid) {
-                float* dst = out + b * out_stride + tl;
+                float* dst = a.dst(b) + tl;
 #pragma unroll
                 for (int r = 0; r < H; ++r) dst[(int64_t)r * W] = v[r];
             }
@@ -229,7 +227,7 @@ k_wave(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t ou
                 }
                 dct3_ortho<W>(v, tww);
                 if (valid) {
-                    float* dst = out + b * out_stride + (int64_t)tl * W;
+                    float* dst = a.dst(b) + (int64_t)tl * W;
 #pragma unroll
                     for (int j = 0; j < W / 4; ++j)
                         *reinterpret_cast<float4*>(dst + 4 * j) =
@@ -244,16 +242,15 @@ k_wave(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t ou
 // Row pass over HBM: one thread per row of length L (rows of `rows` per array).
 template <int L, int DIR>
 __global__ void __launch_bounds__(64)
-k_rows(const float* in, float* out, int64_t batch, int32_t rows, int64_t in_stride,
-       int64_t out_stride, const float2* __restrict__ tw_in)
+k_rows(Addr a, int64_t batch, int32_t rows, const float2* __restrict__ tw_in)
 {
     const twptr tw = (twptr)tw_in;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= batch * rows) return;
     const int64_t b = g / rows;
     const int r = (int)(g % rows);
-    const float* src = in + b * in_stride + (int64_t)r * L;
-    float* dst = out + b * out_stride + (int64_t)r * L;
+    const float* src = a.src(b) + (int64_t)r * L;
+    float* dst = a.dst(b) + (int64_t)r * L;
     float v[L];
 #pragma unroll
     for (int j = 0; j < L / 4; ++j) {
@@ -270,16 +267,15 @@ k_rows(const float* in, float* out, int64_t batch, int32_t rows, int64_t in_stri
 // consecutive columns, so every load/store instruction is contiguous across the wave.
 template <int L, int DIR>
 __global__ void __launch_bounds__(64)
-k_cols(const float* in, float* out, int64_t batch, int32_t cols, int64_t in_stride,
-       int64_t out_stride, const float2* __restrict__ tw_in)
+k_cols(Addr a, int64_t batch, int32_t cols, const float2* __restrict__ tw_in)
 {
     const twptr tw = (twptr)tw_in;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= batch * cols) return;
     const int64_t b = g / cols;
     const int c = (int)(g % cols);
-    const float* src = in + b * in_stride + c;
-    float* dst = out + b * out_stride + c;
+    const float* src = a.src(b) + c;
+    float* dst = a.dst(b) + c;
     float v[L];
 #pragma unroll
     for (int r = 0; r < L; ++r) v[r] = src[(int64_t)r * cols];
@@ -313,16 +309,13 @@ int launch_fused_hw(const DeviceTables* t, const Job& j)
     const unsigned grid = (unsigned)(ntiles < cap ? ntiles : cap);
     switch (j.dir) {
     case DCT2D_FORWARD:
-        k_fused<H, W, DCT2D_FORWARD><<<grid, C::NT, 0, j.stream>>>(j.in, j.out, j.batch, j.in_stride,
-                                                                   j.out_stride, twh, tww);
+        k_fused<H, W, DCT2D_FORWARD><<<grid, C::NT, 0, j.stream>>>(j.addr(), j.batch, twh, tww);
         break;
     case DCT2D_INVERSE:
-        k_fused<H, W, DCT2D_INVERSE><<<grid, C::NT, 0, j.stream>>>(j.in, j.out, j.batch, j.in_stride,
-                                                                   j.out_stride, twh, tww);
+        k_fused<H, W, DCT2D_INVERSE><<<grid, C::NT, 0, j.stream>>>(j.addr(), j.batch, twh, tww);
         break;
     default:
-        k_fused<H, W, DCT2D_ROUNDTRIP><<<grid, C::NT, 0, j.stream>>>(j.in, j.out, j.batch, j.in_stride,
-                                                                     j.out_stride, twh, tww);
+        k_fused<H, W, DCT2D_ROUNDTRIP><<<grid, C::NT, 0, j.stream>>>(j.addr(), j.batch, twh, tww);
         break;
     }
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
@@ -338,8 +331,7 @@ int launch_wave_dir(const DeviceTables* t, const Job& j)
         per_cu = 1;
     const int64_t cap = (int64_t)t->num_cu * per_cu * 4;
     const unsigned grid = (unsigned)(ntiles < cap ? ntiles : cap);
-    k_wave<H, W, DIR><<<grid, 64, 0, j.stream>>>(j.in, j.out, j.batch, j.in_stride, j.out_stride, tw_for(t, H),
-                                                  tw_for(t, W));
+    k_wave<H, W, DIR><<<grid, 64, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, H), tw_for(t, W));
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
 }
 
@@ -377,73 +369,73 @@ int launch_wave(const DeviceTables* t, const Job& j)
 }
 
 template <int L, int DIR>
-void launch_rows(const DeviceTables* t, const float* in, float* out, int64_t batch, int rows,
-                 int64_t is, int64_t os, hipStream_t s)
+void launch_rows(const DeviceTables* t, const Addr& a, int64_t batch, int rows, hipStream_t s)
 {
     const int64_t n = batch * rows;
-    k_rows<L, DIR><<<(unsigned)((n + 63) / 64), 64, 0, s>>>(in, out, batch, rows, is, os, tw_for(t, L));
+    k_rows<L, DIR><<<(unsigned)((n + 63) / 64), 64, 0, s>>>(a, batch, rows, tw_for(t, L));
 }
 
 template <int L, int DIR>
-void launch_cols(const DeviceTables* t, const float* in, float* out, int64_t batch, int cols,
-                 int64_t is, int64_t os, hipStream_t s)
+void launch_cols(const DeviceTables* t, const Addr& a, int64_t batch, int cols, hipStream_t s)
 {
     const int64_t n = batch * cols;
-    k_cols<L, DIR><<<(unsigned)((n + 63) / 64), 64, 0, s>>>(in, out, batch, cols, is, os, tw_for(t, L));
+    k_cols<L, DIR><<<(unsigned)((n + 63) / 64), 64, 0, s>>>(a, batch, cols, tw_for(t, L));
 }
 
 // Row pass with length `len` (runtime) -> template dispatch.
 template <int DIR>
-int rows_any(const DeviceTables* t, int len, const float* in, float* out, int64_t batch, int rows,
-             int64_t is, int64_t os, hipStream_t s)
+int rows_any(const DeviceTables* t, int len, const Addr& a, int64_t batch, int rows, hipStream_t s)
 {
     switch (len) {
-    case 8: launch_rows<8, DIR>(t, in, out, batch, rows, is, os, s); break;
-    case 16: launch_rows<16, DIR>(t, in, out, batch, rows, is, os, s); break;
-    case 32: launch_rows<32, DIR>(t, in, out, batch, rows, is, os, s); break;
-    case 64: launch_rows<64, DIR>(t, in, out, batch, rows, is, os, s); break;
-    case 128: launch_rows<128, DIR>(t, in, out, batch, rows, is, os, s); break;
-    case 256: launch_rows<256, DIR>(t, in, out, batch, rows, is, os, s); break;
+    case 8: launch_rows<8, DIR>(t, a, batch, rows, s); break;
+    case 16: launch_rows<16, DIR>(t, a, batch, rows, s); break;
+    case 32: launch_rows<32, DIR>(t, a, batch, rows, s); break;
+    case 64: launch_rows<64, DIR>(t, a, batch, rows, s); break;
+    case 128: launch_rows<128, DIR>(t, a, batch, rows, s); break;
+    case 256: launch_rows<256, DIR>(t, a, batch, rows, s); break;
     default: return DCT2D_ERR_SIZE;
     }
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
 }
 
 template <int DIR>
-int cols_any(const DeviceTables* t, int len, const float* in, float* out, int64_t batch, int cols,
-             int64_t is, int64_t os, hipStream_t s)
+int cols_any(const DeviceTables* t, int len, const Addr& a, int64_t batch, int cols, hipStream_t s)
 {
     switch (len) {
-    case 8: launch_cols<8, DIR>(t, in, out, batch, cols, is, os, s); break;
-    case 16: launch_cols<16, DIR>(t, in, out, batch, cols, is, os, s); break;
-    case 32: launch_cols<32, DIR>(t, in, out, batch, cols, is, os, s); break;
-    case 64: launch_cols<64, DIR>(t, in, out, batch, cols, is, os, s); break;
-    case 128: launch_cols<128, DIR>(t, in, out, batch, cols, is, os, s); break;
-    case 256: launch_cols<256, DIR>(t, in, out, batch, cols, is, os, s); break;
+    case 8: launch_cols<8, DIR>(t, a, batch, cols, s); break;
+    case 16: launch_cols<16, DIR>(t, a, batch, cols, s); break;
+    case 32: launch_cols<32, DIR>(t, a, batch, cols, s); break;
+    case 64: launch_cols<64, DIR>(t, a, batch, cols, s); break;
+    case 128: launch_cols<128, DIR>(t, a, batch, cols, s); break;
+    case 256: launch_cols<256, DIR>(t, a, batch, cols, s); break;
     default: return DCT2D_ERR_SIZE;
     }
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
 }
 
 // Two-pass schedule over HBM (rows, then columns; the round trip needs a third pass).
+// The first pass reads the input arrays and writes the output arrays; the later
+// passes work in place on the output arrays.
 int launch_two_pass(const DeviceTables* t, const Job& j)
 {
+    const Addr first = j.addr();
+    const Addr inplace{j.out, j.out, j.out_stride, j.out_stride, j.out_idx, j.out_idx, j.out_slot, j.out_slot};
     int rc;
     switch (j.dir) {
     case DCT2D_FORWARD:
-        rc = rows_any<DCT2D_FORWARD>(t, j.cols, j.in, j.out, j.batch, j.rows, j.in_stride, j.out_stride, j.stream);
+        rc = rows_any<DCT2D_FORWARD>(t, j.cols, first, j.batch, j.rows, j.stream);
         if (rc) return rc;
-        return cols_any<DCT2D_FORWARD>(t, j.rows, j.out, j.out, j.batch, j.cols, j.out_stride, j.out_stride, j.stream);
+        return cols_any<DCT2D_FORWARD>(t, j.rows, inplace, j.batch, j.cols, j.stream);
     case DCT2D_INVERSE:
-        rc = rows_any<DCT2D_INVERSE>(t, j.cols, j.in, j.out, j.batch, j.rows, j.in_stride, j.out_stride, j.stream);
+        rc = rows_any<DCT2D_INVERSE>(t, j.cols, first, j.batch, j.rows, j.stream);
         if (rc) return rc;
-        return cols_any<DCT2D_INVERSE>(t, j.rows, j.out, j.out, j.batch, j.cols, j.out_stride, j.out_stride, j.stream);
+        return cols_any<DCT2D_INVERSE>(t, j.rows, inplace, j.batch, j.cols, j.stream);
     default:
-        rc = rows_any<DCT2D_FORWARD>(t, j.cols, j.in, j.out, j.batch, j.rows, j.in_stride, j.out_stride, j.stream);
+        rc = rows_any<DCT2D_FORWARD>(t, j.cols, first, j.batch, j.rows, j.stream);
         if (rc) return rc;
-        rc = cols_any<DCT2D_ROUNDTRIP>(t, j.rows, j.out, j.out, j.batch, j.cols, j.out_stride, j.out_stride, j.stream);
+        rc = cols_any<DCT2D_ROUNDTRIP>(t, j.rows, inplace, j.batch, j.cols, j.stream);
         if (rc) return rc;
-        return rows_any<DCT2D_INVERSE>(t, j.cols, j.out, j.out, j.batch, j.rows, j.out_stride, j.out_stride, j.stream);
+        return rows_any<DCT2D_INVERSE>(t, j.cols, inplace, j.batch, j.rows, j.stream);
     }
 }
 

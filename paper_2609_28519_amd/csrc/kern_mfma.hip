@@ -251,7 +251,7 @@ __device__ __forceinline__ f32x4 pass16(const float (&d)[4], const B16<N, MODE>&
 // Each wavefront processes UNROLL tiles per iteration of its grid-stride loop.
 template <int N, int MODE, int DIR, int UNROLL>
 __global__ void __launch_bounds__(256)
-k_mfma16(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t out_stride, QTab q)
+k_mfma16(Addr a, int64_t batch, QTab q)
 {
     constexpr int BPT = N == 8 ? 4 : 1; // blocks per tile
     constexpr int T0 = ModeInfo<MODE>::target;
@@ -289,7 +289,7 @@ k_mfma16(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t 
             const int64_t b = (t0 + u) * BPT + blk;
             valid[u] = (t0 + u) < ntiles && b < batch;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (valid[u]) v = *reinterpret_cast<const float4*>(in + b * in_stride + off);
+            if (valid[u]) v = *reinterpret_cast<const float4*>(a.src(b) + off);
             d[u][0] = v.x; d[u][1] = v.y; d[u][2] = v.z; d[u][3] = v.w;
         }
 #pragma unroll
@@ -332,7 +332,7 @@ k_mfma16(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t 
             }
             if (valid[u]) {
                 const int64_t b = (t0 + u) * BPT + blk;
-                *reinterpret_cast<float4*>(out + b * out_stride + off) =
+                *reinterpret_cast<float4*>(a.dst(b) + off) =
                     make_float4(ldexpf(d[u][0], etot), ldexpf(d[u][1], etot), ldexpf(d[u][2], etot),
                                 ldexpf(d[u][3], etot));
             }
@@ -436,7 +436,7 @@ __device__ __forceinline__ f32x16 pass32(const float (&d)[16], const B32<MODE>& 
 
 template <int MODE, int DIR, int UNROLL>
 __global__ void __launch_bounds__(256)
-k_mfma32(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t out_stride, QTab q)
+k_mfma32(Addr a, int64_t batch, QTab q)
 {
     constexpr int T0 = ModeInfo<MODE>::target;
     const int lane = threadIdx.x & 63;
@@ -462,7 +462,7 @@ k_mfma32(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t 
 #pragma unroll
             for (int qq = 0; qq < 4; ++qq) {
                 float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (b < batch) v = *reinterpret_cast<const float4*>(in + b * in_stride + c * 32 + 8 * qq + 4 * h);
+                if (b < batch) v = *reinterpret_cast<const float4*>(a.src(b) + c * 32 + 8 * qq + 4 * h);
                 d[u][4 * qq] = v.x; d[u][4 * qq + 1] = v.y; d[u][4 * qq + 2] = v.z; d[u][4 * qq + 3] = v.w;
             }
         }
@@ -497,7 +497,7 @@ k_mfma32(const float* in, float* out, int64_t batch, int64_t in_stride, int64_t 
             if (b < batch) {
 #pragma unroll
                 for (int qq = 0; qq < 4; ++qq)
-                    *reinterpret_cast<float4*>(out + b * out_stride + c * 32 + 8 * qq + 4 * h) =
+                    *reinterpret_cast<float4*>(a.dst(b) + c * 32 + 8 * qq + 4 * h) =
                         make_float4(ldexpf(d[u][4 * qq], etot), ldexpf(d[u][4 * qq + 1], etot),
                                     ldexpf(d[u][4 * qq + 2], etot), ldexpf(d[u][4 * qq + 3], etot));
             }
@@ -522,8 +522,7 @@ int go16(const DeviceTables* t, const Job& j)
     const int64_t cap = (int64_t)t->num_cu * 32; // 8 waves per SIMD
     const int64_t waves = waves_needed < cap ? waves_needed : cap;
     const unsigned grid = (unsigned)((waves + 3) / 4);
-    k_mfma16<N, MODE, DIR, UNROLL><<<grid, 256, 0, j.stream>>>(j.in, j.out, j.batch, j.in_stride, j.out_stride,
-                                                               qtab(t, N));
+    k_mfma16<N, MODE, DIR, UNROLL><<<grid, 256, 0, j.stream>>>(j.addr(), j.batch, qtab(t, N));
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
 }
 
@@ -534,8 +533,7 @@ int go32(const DeviceTables* t, const Job& j)
     const int64_t cap = (int64_t)t->num_cu * 32;
     const int64_t waves = waves_needed < cap ? waves_needed : cap;
     const unsigned grid = (unsigned)((waves + 3) / 4);
-    k_mfma32<MODE, DIR, UNROLL><<<grid, 256, 0, j.stream>>>(j.in, j.out, j.batch, j.in_stride, j.out_stride,
-                                                            qtab(t, 32));
+    k_mfma32<MODE, DIR, UNROLL><<<grid, 256, 0, j.stream>>>(j.addr(), j.batch, qtab(t, 32));
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
 }
 
