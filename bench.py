@@ -38,12 +38,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sizes", default=",".join(map(str, SIZES)))
     ap.add_argument("--precision", default="auto", help="path used by the step (auto = library default)")
-    ap.add_argument("--compare", default="fp32,bf16x3,bf16x6,fp16x3",
+    ap.add_argument("--compare", default="fp32,bf16x3,bf16x6,fp16x3,bf16,fp16,fp8",
                     help="paths timed per size for the float32 vs split comparison (N<=32 for splits)")
-    ap.add_argument("--cpu-frac", type=float, default=0.25, help="fraction of each batch the oracle runs on")
+    ap.add_argument("--cpu-frac", type=float, default=0.75, help="fraction of each batch the oracle runs on")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--log2-floats", type=int, default=27, help="floats per size (default 2^27 = 512 MiB)")
     ap.add_argument("--no-tune", action="store_true", help="skip the (untimed) autotuning pass")
+    ap.add_argument("--save-policy", default="", help="write the tuned policy (autotune cache, JSON) here")
+    ap.add_argument("--load-policy", default="", help="freeze this saved policy instead of tuning")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch (one graph launch) measurement")
     return ap.parse_args()
 
 
@@ -76,27 +79,35 @@ def main():
 
     # ---- autotune (untimed, on the library's own scratch data, before any measurement) --
     tuned = {}
-    if not args.no_tune:
+    if args.load_policy:
+        dct.load_policy(args.load_policy)
+    elif not args.no_tune:
         for n in sizes:
             for d in DIRS:
-                for p in ("fp32",):
-                    if dct.variant_count(n, n, d, p) > 1:
-                        dct.tune(n, n, d, p, batch=(1 << 26) // (n * n), stream=stream)
-                    tuned["%d/%s/%s" % (n, d, p)] = dct.get_variant(n, n, d, p)
+                # tunes the variants of every float32-accurate path, freezes the fastest path for "auto"
+                dct.tune(n, n, d, "auto", batch=(1 << args.log2_floats) // (n * n), stream=stream)
         torch.cuda.synchronize()
+    if args.save_policy:
+        dct.save_policy(args.save_policy)
+    for n in sizes:
+        for d in DIRS:
+            path = dct.get_variant(n, n, d, "auto")
+            name = {v: k for k, v in dct.PRECISIONS.items()}[path]
+            tuned["%d/%s" % (n, d)] = "%s/v%d" % (name, dct.get_variant(n, n, d, name))
 
     def call(n, d, prec, t):
         return dct.transform(t, t, d, prec, stream=stream)
 
-    # ---- self-check before timing (round trip must return the input) -----------------
+    # ---- self-check before timing (the round trip must return the input) -------------
+    # Runs on a full-size copy so every launch of a kernel in this process has the same size.
     for n in sizes:
-        t = bufs[n][:64].clone()
-        x0 = t.clone()
+        t = bufs[n].clone()
         call(n, "roundtrip", args.precision, t)
         torch.cuda.synchronize()
-        num = torch.linalg.vector_norm((t - x0).double().reshape(64, -1), dim=1)
-        den = torch.linalg.vector_norm(x0.double().reshape(64, -1), dim=1)
+        num = torch.linalg.vector_norm((t[:256] - bufs[n][:256]).double().reshape(256, -1), dim=1)
+        den = torch.linalg.vector_norm(bufs[n][:256].double().reshape(256, -1), dim=1)
         worst = float((num / den).max())
+        del t
         if worst > GATE["roundtrip"]:
             print("self-check failed N=%d e_rel %.3e" % (n, worst), file=sys.stderr)
             sys.exit(1)
@@ -176,6 +187,8 @@ def main():
             compare.setdefault(p, {})[str(n)] = round(8 * n * n * host[n].shape[0] / (ms * 1e-3) / 1e9, 1)
             del scratch
 
+    ragged = None if args.no_ragged else ragged_c4(dct, stream, args.steps)
+
     out = {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -185,12 +198,42 @@ def main():
                       "sizes": sizes, "batch": {str(n): int(host[n].shape[0]) for n in sizes},
                       "precision": args.precision, "variants": tuned},
            "hbm_frac": round(value / HBM_PEAK_GBS, 4), "wall_s": round(wall, 3),
-           "roofline": roofline, "per_size": per, "compare_forward_GBps": compare}
+           "roofline": roofline, "per_size": per, "compare_forward_GBps": compare, "ragged_c4": ragged}
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same arrays -----------
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(host, sizes, args.cpu_frac, bufs, stream)
     print(json.dumps(out), flush=True)
+
+
+def ragged_c4(dct, stream, steps):
+    """The ragged configuration: 200k blocks (8..256) + 4 x 1024^2 + 4 x 512x384 images, U[-1,1] with 5%
+    of items x 1e30, forward in place, one hipGraphLaunch per step (plan recorded before timing)."""
+    import torch
+
+    import workloads
+    rg = workloads.c4_ragged()
+    buf = torch.from_numpy(rg.data).cuda()
+    plan = dct.RaggedPlan(rg.offsets, rg.rows, rg.cols, "forward", "auto")
+    info = plan.info()
+    plan.execute(buf, stream)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        plan.execute(buf, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    alg = int(8 * (rg.rows.astype(np.int64) * rg.cols).sum())
+    plan.close()
+    del buf
+    torch.cuda.empty_cache()
+    return {"ms": round(ms, 4), "GB/s": round(alg / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "items": info["items"],
+            "classes": info["classes"], "graph_nodes": info["graph_nodes"], "launches_per_step": 1,
+            "algorithmic_bytes": alg}
 
 
 def cpu_baseline(host, sizes, frac, bufs, stream):

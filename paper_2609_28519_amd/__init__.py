@@ -157,19 +157,24 @@ def transform(inp, out=None, direction="forward", precision="auto", stream=None)
     return out
 
 
+def _p(precision):
+    return PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+
+
+def _d(direction):
+    return DIRECTIONS[direction] if isinstance(direction, str) else int(direction)
+
+
 def variant_count(rows, cols, direction="forward", precision="fp32") -> int:
-    return load().dct2d_variant_count(rows, cols, DIRECTIONS.get(direction, direction),
-                                      PRECISIONS.get(precision, precision))
+    return load().dct2d_variant_count(rows, cols, _d(direction), _p(precision))
 
 
 def set_variant(rows, cols, direction, precision, variant) -> None:
-    _check(load().dct2d_set_variant(rows, cols, DIRECTIONS.get(direction, direction),
-                                    PRECISIONS.get(precision, precision), variant), "dct2d_set_variant")
+    _check(load().dct2d_set_variant(rows, cols, _d(direction), _p(precision), variant), "dct2d_set_variant")
 
 
 def get_variant(rows, cols, direction="forward", precision="fp32") -> int:
-    v = load().dct2d_get_variant(rows, cols, DIRECTIONS.get(direction, direction),
-                                 PRECISIONS.get(precision, precision))
+    v = load().dct2d_get_variant(rows, cols, _d(direction), _p(precision))
     if v < 0:
         raise DCT2DError(v, "dct2d_get_variant")
     return v
@@ -177,9 +182,43 @@ def get_variant(rows, cols, direction="forward", precision="fp32") -> int:
 
 def tune(rows, cols, direction="forward", precision="fp32", batch=4096, stream=None) -> float:
     ms = ctypes.c_float(0)
-    _check(load().dct2d_tune(rows, cols, DIRECTIONS.get(direction, direction), PRECISIONS.get(precision, precision),
-                             batch, ctypes.c_void_p(_stream(stream)), ctypes.byref(ms)), "dct2d_tune")
+    _check(load().dct2d_tune(rows, cols, _d(direction), _p(precision), batch, ctypes.c_void_p(_stream(stream)),
+                             ctypes.byref(ms)), "dct2d_tune")
     return ms.value
+
+
+SIZES = (8, 16, 32, 64, 128, 256)
+
+
+def policy() -> dict:
+    """The frozen per-size policy: variant of every (rows, cols, direction, path) and the
+    float32-accurate path chosen for "auto" (the autotune cache, as a JSON-able dict)."""
+    out = {}
+    for r in SIZES:
+        for c in SIZES:
+            for dname, d in DIRECTIONS.items():
+                key = "%dx%d/%s" % (r, c, dname)
+                out[key + "/auto"] = get_variant(r, c, d, AUTO)
+                for pname, p in PRECISIONS.items():
+                    if p != AUTO and variant_count(r, c, d, p) > 0:
+                        out["%s/%s" % (key, pname)] = get_variant(r, c, d, p)
+    return out
+
+
+def save_policy(path: str) -> None:
+    import json
+    with open(path, "w") as f:
+        json.dump(policy(), f, indent=0, sort_keys=True)
+
+
+def load_policy(path: str) -> None:
+    """Freezes a policy written by save_policy (auto paths last, after the variants)."""
+    import json
+    pol = json.load(open(path))
+    for key, v in sorted(pol.items(), key=lambda kv: kv[0].endswith("/auto")):
+        shape, dname, pname = key.split("/")
+        r, c = (int(x) for x in shape.split("x"))
+        set_variant(r, c, dname, pname, int(v))
 
 
 class RaggedPlan:
