@@ -41,6 +41,18 @@ struct cf {
     float x, y;
 };
 
+// Re-reads of the twiddle pointer: an optimisation barrier that stops the compiler from
+// hoisting every twiddle load of a long transform to its start (which would pin them all
+// in scalar registers and spill).  A no-op on the host.
+__host__ __device__ __forceinline__ void tw_fence(twptr& tw)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+s"(tw));
+#else
+    (void)tw;
+#endif
+}
+
 __host__ __device__ __forceinline__ cf cadd(cf a, cf b) { return {a.x + b.x, a.y + b.y}; }
 __host__ __device__ __forceinline__ cf csub(cf a, cf b) { return {a.x - b.x, a.y - b.y}; }
 __host__ __device__ __forceinline__ cf cconj(cf a) { return {a.x, -a.y}; }
@@ -144,14 +156,17 @@ __host__ __device__ __forceinline__ void fft_rec(const cf* in, cf* out, twptr tw
 
 // y <- sqrt(2/L) DCT-IV_M(w): one length-M/2 complex FFT between two twiddle products.
 template <int L, int M>
-__host__ __device__ __forceinline__ void dct4_scaled(const float* w, float* y, twptr tw)
+__host__ __device__ __forceinline__ void dct4_scaled(const float* w, float* y, twptr tw_in)
 {
     using T = TwLayout<L>;
     constexpr int H = M / 2;
+    twptr tw = tw_in;
     cf t[H], c[H];
 #pragma unroll
     for (int n = 0; n < H; ++n) t[n] = cmul(cf{w[2 * n], w[M - 1 - 2 * n]}, tw[T::pre(M) + n]);
+    if (M >= 32) tw_fence(tw);
     fft_rec<H, 1, false, T::FFT_TOP>(t, c, tw);
+    if (M >= 32) tw_fence(tw);
 #pragma unroll
     for (int k = 0; k < H; ++k) {
         // q = conj(post twiddle):  Re(c p) = c.x q.x + c.y q.y,  -Im(c p) = c.x q.y - c.y q.x
@@ -177,8 +192,11 @@ __host__ __device__ __forceinline__ void dct2_rec(const float* x, float* X, twpt
             u[n] = x[n] + x[N - 1 - n];
             w[n] = x[n] - x[N - 1 - n];
         }
-        dct2_rec<L, H>(u, ue, tw);
-        dct4_scaled<L, H>(w, wo, tw);
+        twptr tw2 = tw;
+        if (N >= 64) tw_fence(tw2);
+        dct2_rec<L, H>(u, ue, tw2);
+        if (N >= 64) tw_fence(tw2);
+        dct4_scaled<L, H>(w, wo, tw2);
 #pragma unroll
         for (int k = 0; k < H; ++k) {
             X[2 * k] = ue[k];
@@ -204,8 +222,11 @@ __host__ __device__ __forceinline__ void dct3_rec(const float* Y, float* x, twpt
             ye[k] = Y[2 * k];
             yo[k] = Y[2 * k + 1];
         }
-        dct3_rec<L, H>(ye, u, tw);
-        dct4_scaled<L, H>(yo, w, tw);
+        twptr tw2 = tw;
+        if (N >= 64) tw_fence(tw2);
+        dct3_rec<L, H>(ye, u, tw2);
+        if (N >= 64) tw_fence(tw2);
+        dct4_scaled<L, H>(yo, w, tw2);
 #pragma unroll
         for (int n = 0; n < H; ++n) {
             x[n] = u[n] + w[n];

@@ -48,6 +48,16 @@ inline const float2* tw_for(const DeviceTables* t, int L)
 
 inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Global-address-space views of float data: kernels access arrays through these so
+// the loads and stores compile to global (not flat) memory instructions.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define DCT_GLOBAL __attribute__((address_space(1)))
+#else
+#define DCT_GLOBAL
+#endif
+typedef DCT_GLOBAL float gfloat;
+typedef DCT_GLOBAL float4 gfloat4;
+
 // ---- array addressing ---------------------------------------------------------------
 // Array b of a batch starts at in + in_idx[b] (indexed: ragged batches) or at
 // in + b * in_stride (strided batches); likewise for the output.  When a slot is
@@ -61,15 +71,15 @@ struct Addr {
     const int64_t* out_idx; // nullptr: strided
     float* const* in_slot;  // nullptr: base = in
     float* const* out_slot; // nullptr: base = out
-    __device__ __forceinline__ const float* src(int64_t b) const
+    __device__ __forceinline__ const gfloat* src(int64_t b) const
     {
-        const float* base = in_slot ? *in_slot : in;
-        return base + (in_idx ? in_idx[b] : b * in_stride);
+        const float* base = in_slot ? *(const gfloat* const DCT_GLOBAL*)in_slot : in;
+        return (const gfloat*)base + (in_idx ? ((const DCT_GLOBAL int64_t*)in_idx)[b] : b * in_stride);
     }
-    __device__ __forceinline__ float* dst(int64_t b) const
+    __device__ __forceinline__ gfloat* dst(int64_t b) const
     {
-        float* base = out_slot ? *out_slot : out;
-        return base + (out_idx ? out_idx[b] : b * out_stride);
+        float* base = out_slot ? *(gfloat* const DCT_GLOBAL*)out_slot : out;
+        return (gfloat*)base + (out_idx ? ((const DCT_GLOBAL int64_t*)out_idx)[b] : b * out_stride);
     }
 };
 

@@ -23,7 +23,7 @@ constexpr int BM = 64, BN = 64, BK = 16;
 
 // Generic strided operand: element (i, k) at p[i * si + k * sk].
 struct Mat {
-    const float* p;
+    const gfloat* p;
     int64_t si, sk;
 };
 
@@ -37,8 +37,8 @@ k_dense_pass(Addr a, bool img_is_a, Mat qm, int64_t img_si, int64_t img_sk, int 
     __shared__ __attribute__((aligned(16))) float Bs[BK][BN + 4];
     const int t = threadIdx.x;
     const int z = blockIdx.z;
-    const float* img = a.src(z);
-    float* dst = a.dst(z);
+    const gfloat* img = a.src(z);
+    gfloat* dst = a.dst(z);
     const Mat A = img_is_a ? Mat{img, img_si, img_sk} : qm;
     const Mat B = img_is_a ? qm : Mat{img, img_si, img_sk}; // B(k, j) = B.p[k * B.si + j * B.sk]
     const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
@@ -108,14 +108,14 @@ int launch_dense_axis(const Addr& a, int64_t count, int rows, int cols, bool col
     if (column_pass) {
         // Y (rows x cols) = Qop (rows x rows) X (rows x cols); Qop = Q or Q^T
         M = rows; N = cols; K = rows;
-        qm = inverse ? Mat{q, 1, rows} : Mat{q, rows, 1};
+        qm = inverse ? Mat{(const gfloat*)q, 1, rows} : Mat{(const gfloat*)q, rows, 1};
         img_is_a = false;
         img_si = cols; img_sk = 1; // B(k, j) = X[k][j]
     } else {
         // Y (rows x cols) = X (rows x cols) Qop (cols x cols); Qop = Q^T (fwd) or Q (inv)
         M = rows; N = cols; K = cols;
         // B(k, j): forward Q^T -> Q[j][k] = q[j*cols + k]: B.si (k stride) = 1, B.sk (j stride) = cols
-        qm = inverse ? Mat{q, cols, 1} : Mat{q, 1, cols};
+        qm = inverse ? Mat{(const gfloat*)q, cols, 1} : Mat{(const gfloat*)q, 1, cols};
         img_is_a = true;
         img_si = cols; img_sk = 1; // A(i, k) = X[i][k]
     }

@@ -110,7 +110,7 @@ k_fused(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* 
                 const int b = c / C::CPB, q = c % C::CPB;
                 const int r = q / (W / 4), c4 = q % (W / 4);
                 float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (b0 + b < batch) v = *reinterpret_cast<const float4*>(a.src(b0 + b) + 4 * q);
+                if (b0 + b < batch) v = *reinterpret_cast<const gfloat4*>(a.src(b0 + b) + 4 * q);
                 *reinterpret_cast<float4*>(lds + b * C::BS + r * C::P + 4 * c4) = v;
             }
         }
@@ -138,7 +138,7 @@ k_fused(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* 
                 const int b = c / C::CPB, q = c % C::CPB;
                 const int r = q / (W / 4), c4 = q % (W / 4);
                 const float4 v = *reinterpret_cast<const float4*>(lds + b * C::BS + r * C::P + 4 * c4);
-                if (b0 + b < batch) *reinterpret_cast<float4*>(a.dst(b0 + b) + 4 * q) = v;
+                if (b0 + b < batch) *reinterpret_cast<gfloat4*>(a.dst(b0 + b) + 4 * q) = v;
             }
         }
         __syncthreads();
@@ -176,17 +176,17 @@ k_wave(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* _
     const int64_t ntiles = (batch + C::BPW - 1) / C::BPW;
     float* tile_lds = lds + tb * C::BS;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const twptr twh = per_iteration(twh_in);
-        const twptr tww = per_iteration(tww_in);
+        twptr twh = per_iteration(twh_in);
+        twptr tww = per_iteration(tww_in);
         const int64_t b = tile * C::BPW + tb;
         const bool valid = b < batch;
         if (tl < H) {
             float v[W];
             if (valid) {
-                const float* src = a.src(b) + (int64_t)tl * W;
+                const gfloat* src = a.src(b) + (int64_t)tl * W;
 #pragma unroll
                 for (int j = 0; j < W / 4; ++j) {
-                    const float4 q = *reinterpret_cast<const float4*>(src + 4 * j);
+                    const float4 q = *reinterpret_cast<const gfloat4*>(src + 4 * j);
                     v[4 * j] = q.x; v[4 * j + 1] = q.y; v[4 * j + 2] = q.z; v[4 * j + 3] = q.w;
                 }
             } else {
@@ -200,6 +200,7 @@ k_wave(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* _
                 *reinterpret_cast<float4*>(row + 4 * j) = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
         }
         __syncthreads();
+        twh = per_iteration(twh_in); // the column pass re-reads its twiddles (see per_iteration)
         if (tl < W) {
             float v[H];
             float* col = tile_lds + tl;
@@ -210,13 +211,14 @@ k_wave(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* _
 #pragma unroll
                 for (int r = 0; r < H; ++r) col[r * C::P] = v[r];
             } else if (valid) {
-                float* dst = a.dst(b) + tl;
+                gfloat* dst = a.dst(b) + tl;
 #pragma unroll
                 for (int r = 0; r < H; ++r) dst[(int64_t)r * W] = v[r];
             }
         }
         if (DIR == DCT2D_ROUNDTRIP) {
             __syncthreads();
+            tww = per_iteration(tww_in);
             if (tl < H) {
                 float v[W];
                 const float* row = tile_lds + tl * C::P;
@@ -227,15 +229,242 @@ k_wave(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* _
                 }
                 dct3_ortho<W>(v, tww);
                 if (valid) {
-                    float* dst = a.dst(b) + (int64_t)tl * W;
+                    gfloat* dst = a.dst(b) + (int64_t)tl * W;
 #pragma unroll
                     for (int j = 0; j < W / 4; ++j)
-                        *reinterpret_cast<float4*>(dst + 4 * j) =
+                        *reinterpret_cast<gfloat4*>(dst + 4 * j) =
                             make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
                 }
             }
         }
         __syncthreads();
+    }
+}
+
+// Split fused kernel for 128 x 128 arrays: one 256-thread workgroup per array.  Every
+// length-128 transform is shared by two wavefronts through the top level of the
+// even/odd recursion (dct1d.hpp): the "even" wavefronts (0, 1) work on
+// u[n] = x[n] + x[127-n] -> DCT-II_64 (even outputs), the "odd" wavefronts (2, 3) on
+// w[n] = x[n] - x[127-n] -> DCT-IV_64 (odd outputs); for the inverse, DCT-III_64 of the
+// even and DCT-IV_64 of the odd coefficients, recombined as a + b and a - b.  The role
+// is uniform per wavefront (no divergence), each thread holds 64 values, and the
+// array's intermediate lives in one LDS tile of odd pitch 129 (conflict-free for the
+// stride-2 row writes and the column reads).
+//   forward:    rows (HBM -> regs -> LDS)  | columns (LDS -> regs -> HBM, lanes = columns)
+//   inverse:    columns (HBM -> regs -> LDS, a|b halves) | rows (LDS, recombined on read)
+//               -> a|b halves in LDS | coalesced recombining store
+//   round trip: forward rows | forward + inverse columns in registers | inverse rows
+constexpr int S128_P = 129;
+
+template <int DIR>
+__global__ void __launch_bounds__(256)
+k_split128(Addr a, int64_t batch, const float2* __restrict__ tw_in)
+{
+    constexpr int L = 128, H = 64, P = S128_P;
+    __shared__ float T[L * P];
+    const int t = threadIdx.x;
+    const int role = t >> 7;       // 0: even half, 1: odd half (uniform per wavefront)
+    const int idx = t & 127;       // row or column handled by this thread
+    for (int64_t blk = blockIdx.x; blk < batch; blk += gridDim.x) {
+        twptr tw = per_iteration(tw_in);
+        const gfloat* src = a.src(blk);
+        gfloat* dst = a.dst(blk);
+        float v[H], o[H];
+        if (DIR != DCT2D_INVERSE) {
+            // ---- forward rows: row idx from HBM --------------------------------------
+            const gfloat* row = src + (int64_t)idx * L;
+#pragma unroll
+            for (int j = 0; j < H / 4; ++j) {
+                const float4 lo = *reinterpret_cast<const gfloat4*>(row + 4 * j);
+                const float4 hi = *reinterpret_cast<const gfloat4*>(row + L - 4 - 4 * j);
+                const float xl[4] = {lo.x, lo.y, lo.z, lo.w};
+                const float xh[4] = {hi.w, hi.z, hi.y, hi.x}; // x[127 - (4j + i)]
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[4 * j + i] = role == 0 ? xl[i] + xh[i] : xl[i] - xh[i];
+            }
+            if (role == 0) dct2_rec<L, H>(v, o, tw); else dct4_scaled<L, H>(v, o, tw);
+#pragma unroll
+            for (int k = 0; k < H; ++k) T[idx * P + 2 * k + role] = o[k];
+            __syncthreads();
+            // ---- forward columns: column idx from LDS ---------------------------------
+#pragma unroll
+            for (int n = 0; n < H; ++n) {
+                const float xl = T[n * P + idx], xh = T[(L - 1 - n) * P + idx];
+                v[n] = role == 0 ? xl + xh : xl - xh;
+            }
+            if (role == 0) dct2_rec<L, H>(v, o, tw); else dct4_scaled<L, H>(v, o, tw);
+            if (DIR == DCT2D_FORWARD) {
+#pragma unroll
+                for (int k = 0; k < H; ++k) dst[(int64_t)(2 * k + role) * L + idx] = o[k];
+                __syncthreads(); // LDS reuse by the next array
+                continue;
+            }
+            // round trip: inverse columns on the same data (even -> DCT-III_64, odd -> DCT-IV_64)
+            asm volatile("" : "+s"(tw));
+            if (role == 0) dct3_rec<L, H>(o, v, tw); else dct4_scaled<L, H>(o, v, tw);
+            __syncthreads(); // every column read before the halves overwrite it
+#pragma unroll
+            for (int n = 0; n < H; ++n) T[(role * H + n) * P + idx] = v[n];
+        } else {
+            // ---- inverse columns: even (role 0) or odd (role 1) coefficient rows from HBM
+#pragma unroll
+            for (int k = 0; k < H; ++k) o[k] = src[(int64_t)(2 * k + role) * L + idx];
+            if (role == 0) dct3_rec<L, H>(o, v, tw); else dct4_scaled<L, H>(o, v, tw);
+#pragma unroll
+            for (int n = 0; n < H; ++n) T[(role * H + n) * P + idx] = v[n];
+        }
+        __syncthreads();
+        // ---- inverse rows.  LDS holds the column results as halves: rows 0..63 = a,
+        // rows 64..127 = b, with Z[n] = a[n] + b[n], Z[127-n] = a[n] - b[n].
+        {
+            const bool top = idx < H;
+            const int rr = top ? idx : L - 1 - idx;
+            const float sg = top ? 1.f : -1.f;
+#pragma unroll
+            for (int k = 0; k < H; ++k) {
+                const int c = 2 * k + role;
+                o[k] = T[rr * P + c] + sg * T[(H + rr) * P + c];
+            }
+        }
+        if (role == 0) dct3_rec<L, H>(o, v, tw); else dct4_scaled<L, H>(o, v, tw);
+        __syncthreads(); // all reads of the column halves done
+#pragma unroll
+        for (int n = 0; n < H; ++n) T[idx * P + role * H + n] = v[n];
+        __syncthreads();
+        // ---- store: x[r][n] = a[n] + b[n], x[r][127-n] = a[n] - b[n]; 4 columns per thread
+#pragma unroll
+        for (int i = 0; i < L * L / (4 * 256); ++i) {
+            const int e = (i * 256 + t) * 4;
+            const int r = e / L, c0 = e % L;
+            float q[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int c = c0 + m;
+                q[m] = c < H ? T[r * P + c] + T[r * P + H + c]
+                             : T[r * P + (L - 1 - c)] - T[r * P + H + (L - 1 - c)];
+            }
+            *reinterpret_cast<gfloat4*>(dst + e) = make_float4(q[0], q[1], q[2], q[3]);
+        }
+        __syncthreads();
+    }
+}
+
+// Fused kernel for 256 x 256 arrays (256 KB, larger than LDS): one 256-thread workgroup
+// per array.  Thread t transforms row t in registers (a whole length-256 transform);
+// the column pass then runs in two rounds of 128 columns through a 256 x 128 LDS tile
+// (pitch 129).  In a round, column c is shared by two wavefronts as in k_split128:
+// role 0 handles the even half (DCT-II_128 / DCT-III_128), role 1 the odd half
+// (DCT-IV_128); for the inverse the two halves are recombined (a + b, a - b) through
+// LDS before a coalesced store (consecutive lanes = consecutive columns).  The second
+// 128 columns of a transformed row wait in the thread's own output row (re-read by the
+// same thread in the second round), which keeps the register footprint of the column
+// rounds free of them.
+//   forward:  rows (HBM -> regs) | 2 x [regs -> LDS -> column halves -> HBM]
+//   inverse:  rows (inverse, HBM -> regs) | 2 x [regs -> LDS -> halves -> LDS -> HBM]
+//   round trip: forward rows | 2 x [forward + inverse column halves -> HBM] | inverse
+//               rows (the column-inverted intermediate is re-read from the array's own
+//               memory after a workgroup barrier)
+constexpr int S256_P = 129;
+
+template <int DIR>
+__global__ void __launch_bounds__(256)
+k_split256(Addr a, int64_t batch, const float2* __restrict__ tw_in)
+{
+    constexpr int L = 256, H = 128, P = S256_P;
+    __shared__ float T[L * P];
+    const int t = threadIdx.x;
+    const int role = t >> 7; // column passes: 0 even half, 1 odd half (uniform per wavefront)
+    const int c = t & 127;   // column within the round
+    for (int64_t blk = blockIdx.x; blk < batch; blk += gridDim.x) {
+        twptr tw = per_iteration(tw_in);
+        const gfloat* src = a.src(blk);
+        gfloat* dst = a.dst(blk);
+        float y[L];
+        {
+            const gfloat* row = src + (int64_t)t * L;
+#pragma unroll
+            for (int j = 0; j < L / 4; ++j) {
+                const float4 q = *reinterpret_cast<const gfloat4*>(row + 4 * j);
+                y[4 * j] = q.x; y[4 * j + 1] = q.y; y[4 * j + 2] = q.z; y[4 * j + 3] = q.w;
+            }
+        }
+        if (DIR == DCT2D_INVERSE) dct3_ortho<L>(y, tw); else dct2_ortho<L>(y, tw);
+        // Park the second half of the transformed row in this thread's own output row
+        // (already consumed as input by this same thread) until the second round, so no
+        // thread keeps 128 extra values live through the first column round.
+        {
+            gfloat* prow = dst + (int64_t)t * L + H;
+#pragma unroll
+            for (int j = 0; j < H / 4; ++j)
+                *reinterpret_cast<gfloat4*>(prow + 4 * j) =
+                    make_float4(y[H + 4 * j], y[H + 4 * j + 1], y[H + 4 * j + 2], y[H + 4 * j + 3]);
+        }
+#pragma unroll
+        for (int round = 0; round < 2; ++round) {
+            asm volatile("" : "+s"(tw));
+            if (round == 0) {
+#pragma unroll
+                for (int j = 0; j < H; ++j) T[t * P + j] = y[j];
+            } else {
+                const gfloat* prow = dst + (int64_t)t * L + H;
+#pragma unroll
+                for (int j = 0; j < H / 4; ++j) {
+                    const float4 q = *reinterpret_cast<const gfloat4*>(prow + 4 * j);
+                    T[t * P + 4 * j] = q.x; T[t * P + 4 * j + 1] = q.y;
+                    T[t * P + 4 * j + 2] = q.z; T[t * P + 4 * j + 3] = q.w;
+                }
+            }
+            __syncthreads();
+            float v[H], o[H];
+            if (DIR != DCT2D_INVERSE) {
+#pragma unroll
+                for (int n = 0; n < H; ++n) {
+                    const float xl = T[n * P + c], xh = T[(L - 1 - n) * P + c];
+                    v[n] = role == 0 ? xl + xh : xl - xh;
+                }
+                if (role == 0) dct2_rec<L, H>(v, o, tw); else dct4_scaled<L, H>(v, o, tw);
+                if (DIR == DCT2D_FORWARD) {
+#pragma unroll
+                    for (int k = 0; k < H; ++k) dst[(int64_t)(2 * k + role) * L + H * round + c] = o[k];
+                    __syncthreads(); // the next round overwrites the tile
+                    continue;
+                }
+                asm volatile("" : "+s"(tw));
+                if (role == 0) dct3_rec<L, H>(o, v, tw); else dct4_scaled<L, H>(o, v, tw);
+            } else {
+#pragma unroll
+                for (int k = 0; k < H; ++k) o[k] = T[(2 * k + role) * P + c];
+                if (role == 0) dct3_rec<L, H>(o, v, tw); else dct4_scaled<L, H>(o, v, tw);
+            }
+            __syncthreads(); // every column read before the halves overwrite the tile
+#pragma unroll
+            for (int n = 0; n < H; ++n) T[(role * H + n) * P + c] = v[n];
+            __syncthreads();
+            // recombine: column value x[n] = a[n] + b[n], x[255-n] = a[n] - b[n]
+#pragma unroll
+            for (int n = 0; n < H; ++n) {
+                const float av = T[n * P + c], bv = T[(H + n) * P + c];
+                const int r = role == 0 ? n : L - 1 - n;
+                dst[(int64_t)r * L + H * round + c] = role == 0 ? av + bv : av - bv;
+            }
+            __syncthreads();
+        }
+        if (DIR == DCT2D_ROUNDTRIP) {
+            // inverse rows on the column-inverted intermediate written above by this workgroup
+            const gfloat* row = dst + (int64_t)t * L;
+#pragma unroll
+            for (int j = 0; j < L / 4; ++j) {
+                const float4 q = *reinterpret_cast<const gfloat4*>(row + 4 * j);
+                y[4 * j] = q.x; y[4 * j + 1] = q.y; y[4 * j + 2] = q.z; y[4 * j + 3] = q.w;
+            }
+            asm volatile("" : "+s"(tw));
+            dct3_ortho<L>(y, tw);
+            gfloat* orow = dst + (int64_t)t * L;
+#pragma unroll
+            for (int j = 0; j < L / 4; ++j)
+                *reinterpret_cast<gfloat4*>(orow + 4 * j) = make_float4(y[4 * j], y[4 * j + 1], y[4 * j + 2], y[4 * j + 3]);
+            __syncthreads();
+        }
     }
 }
 
@@ -249,18 +478,18 @@ k_rows(Addr a, int64_t batch, int32_t rows, const float2* __restrict__ tw_in)
     if (g >= batch * rows) return;
     const int64_t b = g / rows;
     const int r = (int)(g % rows);
-    const float* src = a.src(b) + (int64_t)r * L;
-    float* dst = a.dst(b) + (int64_t)r * L;
+    const gfloat* src = a.src(b) + (int64_t)r * L;
+    gfloat* dst = a.dst(b) + (int64_t)r * L;
     float v[L];
 #pragma unroll
     for (int j = 0; j < L / 4; ++j) {
-        const float4 q = *reinterpret_cast<const float4*>(src + 4 * j);
+        const float4 q = *reinterpret_cast<const gfloat4*>(src + 4 * j);
         v[4 * j] = q.x; v[4 * j + 1] = q.y; v[4 * j + 2] = q.z; v[4 * j + 3] = q.w;
     }
     apply1d<L, DIR>(v, tw);
 #pragma unroll
     for (int j = 0; j < L / 4; ++j)
-        *reinterpret_cast<float4*>(dst + 4 * j) = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+        *reinterpret_cast<gfloat4*>(dst + 4 * j) = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
 }
 
 // Column pass over HBM: one thread per column of length L; consecutive lanes take
@@ -274,8 +503,8 @@ k_cols(Addr a, int64_t batch, int32_t cols, const float2* __restrict__ tw_in)
     if (g >= batch * cols) return;
     const int64_t b = g / cols;
     const int c = (int)(g % cols);
-    const float* src = a.src(b) + c;
-    float* dst = a.dst(b) + c;
+    const gfloat* src = a.src(b) + c;
+    gfloat* dst = a.dst(b) + c;
     float v[L];
 #pragma unroll
     for (int r = 0; r < L; ++r) v[r] = src[(int64_t)r * cols];
@@ -365,6 +594,48 @@ int launch_wave(const DeviceTables* t, const Job& j)
     case 32: return wave_w<32>(t, j);
     case 64: return wave_w<64>(t, j);
     default: return DCT2D_ERR_SIZE;
+    }
+}
+
+template <int DIR>
+int launch_split128_dir(const DeviceTables* t, const Job& j)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_split128<DIR>, 256, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int64_t cap = (int64_t)t->num_cu * per_cu * 4;
+    const unsigned grid = (unsigned)(j.batch < cap ? j.batch : cap);
+    k_split128<DIR><<<grid, 256, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, 128));
+    return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
+}
+
+int launch_split128(const DeviceTables* t, const Job& j)
+{
+    switch (j.dir) {
+    case DCT2D_FORWARD: return launch_split128_dir<DCT2D_FORWARD>(t, j);
+    case DCT2D_INVERSE: return launch_split128_dir<DCT2D_INVERSE>(t, j);
+    default: return launch_split128_dir<DCT2D_ROUNDTRIP>(t, j);
+    }
+}
+
+template <int DIR>
+int launch_split256_dir(const DeviceTables* t, const Job& j)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_split256<DIR>, 256, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const int64_t cap = (int64_t)t->num_cu * per_cu * 4;
+    const unsigned grid = (unsigned)(j.batch < cap ? j.batch : cap);
+    k_split256<DIR><<<grid, 256, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, 256));
+    return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
+}
+
+int launch_split256(const DeviceTables* t, const Job& j)
+{
+    switch (j.dir) {
+    case DCT2D_FORWARD: return launch_split256_dir<DCT2D_FORWARD>(t, j);
+    case DCT2D_INVERSE: return launch_split256_dir<DCT2D_INVERSE>(t, j);
+    default: return launch_split256_dir<DCT2D_ROUNDTRIP>(t, j);
     }
 }
 
@@ -468,12 +739,16 @@ int launch_fused(const DeviceTables* t, const Job& j)
 
 // Variants (frozen per size by the policy table / autotuner):
 //   both axes <= 64:  0 wave-local fused, 1 LDS-staged fused, 2 two-pass
-//   an axis of 128:   0 LDS-staged fused, 1 two-pass
-//   an axis of 256:   0 two-pass
+//   128 x 128:        0 split fused (two wavefronts per transform), 1 LDS-staged fused, 2 two-pass
+//   other axes <=128: 0 LDS-staged fused, 1 two-pass
+//   256 x 256:        0 fused (rows in registers, columns in two LDS rounds), 1 two-pass
+//   other, an axis of 256: 0 two-pass
 int fp32_variant_count(int rows, int cols, int)
 {
     if (rows <= 64 && cols <= 64) return 3;
+    if (rows == 128 && cols == 128) return 3;
     if (rows <= 128 && cols <= 128) return 2;
+    if (rows == 256 && cols == 256) return 2;
     return 1;
 }
 
@@ -484,7 +759,13 @@ int launch_fp32(const DeviceTables* t, const Job& j)
         if (j.variant == 1) return launch_fused(t, j);
         return launch_two_pass(t, j);
     }
+    if (j.rows == 128 && j.cols == 128) {
+        if (j.variant == 0) return launch_split128(t, j);
+        if (j.variant == 1) return launch_fused(t, j);
+        return launch_two_pass(t, j);
+    }
     if (j.rows <= 128 && j.cols <= 128 && j.variant == 0) return launch_fused(t, j);
+    if (j.rows == 256 && j.cols == 256 && j.variant == 0) return launch_split256(t, j);
     return launch_two_pass(t, j);
 }
 

@@ -1,4 +1,4 @@
-// Dense matrix paths on MFMA for N = 8, 16, 32 (and the 64 = 2x2-tile form):
+// Dense matrix paths on MFMA for N = 8, 16, 32 and 64 (64 as 2 x 2 tiles of the 32 x 32 form):
 // Y = Q X Q^T (eq. 2) as two small matrix products per block, with float32 accuracy
 // recovered from low-precision operands by splitting (split-precision products) and
 // a power-of-two scale per block.
@@ -289,7 +289,7 @@ k_mfma16(Addr a, int64_t batch, QTab q)
             const int64_t b = (t0 + u) * BPT + blk;
             valid[u] = (t0 + u) < ntiles && b < batch;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (valid[u]) v = *reinterpret_cast<const float4*>(a.src(b) + off);
+            if (valid[u]) v = *reinterpret_cast<const gfloat4*>(a.src(b) + off);
             d[u][0] = v.x; d[u][1] = v.y; d[u][2] = v.z; d[u][3] = v.w;
         }
 #pragma unroll
@@ -332,7 +332,7 @@ k_mfma16(Addr a, int64_t batch, QTab q)
             }
             if (valid[u]) {
                 const int64_t b = (t0 + u) * BPT + blk;
-                *reinterpret_cast<float4*>(a.dst(b) + off) =
+                *reinterpret_cast<gfloat4*>(a.dst(b) + off) =
                     make_float4(ldexpf(d[u][0], etot), ldexpf(d[u][1], etot), ldexpf(d[u][2], etot),
                                 ldexpf(d[u][3], etot));
             }
@@ -462,7 +462,7 @@ k_mfma32(Addr a, int64_t batch, QTab q)
 #pragma unroll
             for (int qq = 0; qq < 4; ++qq) {
                 float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (b < batch) v = *reinterpret_cast<const float4*>(a.src(b) + c * 32 + 8 * qq + 4 * h);
+                if (b < batch) v = *reinterpret_cast<const gfloat4*>(a.src(b) + c * 32 + 8 * qq + 4 * h);
                 d[u][4 * qq] = v.x; d[u][4 * qq + 1] = v.y; d[u][4 * qq + 2] = v.z; d[u][4 * qq + 3] = v.w;
             }
         }
@@ -497,11 +497,205 @@ k_mfma32(Addr a, int64_t batch, QTab q)
             if (b < batch) {
 #pragma unroll
                 for (int qq = 0; qq < 4; ++qq)
-                    *reinterpret_cast<float4*>(a.dst(b) + c * 32 + 8 * qq + 4 * h) =
+                    *reinterpret_cast<gfloat4*>(a.dst(b) + c * 32 + 8 * qq + 4 * h) =
                         make_float4(ldexpf(d[u][4 * qq], etot), ldexpf(d[u][4 * qq + 1], etot),
                                     ldexpf(d[u][4 * qq + 2], etot), ldexpf(d[u][4 * qq + 3], etot));
             }
         }
+    }
+}
+
+// ---- 64 x 64 blocks as 2 x 2 tiles of the 32 x 32 form ---------------------------------
+// The exact 64-point product Q_64 X Q_64^T with Q_64 cut into four 32 x 32 tiles: output
+// tile (I, J) of a pass is sum_K A(I, K) B(K, J), eight tile products per pass.  The
+// accumulator of tile (K, I) after pass 1 serves as the A operand of tile (I, K) in pass 2
+// (the same transpose-by-reuse as the 32 x 32 kernel, applied tile-wise).
+// B tile (K, J) of Q^T (forward) or Q (inverse), split part p, in the lane's slots:
+// bt[p][s][j] = B[32 K + k(s, j)][32 J + c].  Read from the (cache-resident) tables at use.
+template <int MODE>
+__device__ __forceinline__ void load_b64_tile(float (&bt)[3][2][8], const QTab& q, bool inv, int h, int c, int K,
+                                              int J)
+{
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = 32 * K + 8 * (2 * s + j / 4) + 4 * h + (j & 3);
+                const int n = 32 * J + c;
+                float v = 0.f;
+                if (p < ModeInfo<MODE>::parts) {
+                    const int r = inv ? k : n, cc = inv ? n : k; // B = Q (inverse) or Q^T
+                    const int i = r * 64 + cc;
+                    v = ModeInfo<MODE>::f16 ? f16_bits_to_f(q.hf[p * 4096 + i]) : bf16_bits_to_f(q.bf[p * 4096 + i]);
+                }
+                bt[p][s][j] = v;
+            }
+}
+
+template <int MODE>
+__device__ __forceinline__ long load_b64_f8(const QTab& q, bool inv, int h, int c, int K, int J, int s)
+{
+    uint64_t v = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int k = 32 * K + 8 * (2 * s + j / 4) + 4 * h + (j & 3);
+        const int n = 32 * J + c;
+        const uint8_t byte = inv ? q.f8[k * 64 + n] : q.f8[n * 64 + k];
+        v |= (uint64_t)byte << (8 * j);
+    }
+    return (long)v;
+}
+
+// acc(I, J) += A(I, K) * B(K, J) over the kept split products; a = the lane's 16 values of
+// the A tile, already split into parts x[part][16].
+template <int MODE>
+__device__ __forceinline__ void tile_products(f32x16& acc, const float (&x)[3][16], const float (&bq)[3][2][8])
+{
+    constexpr int P = ModeInfo<MODE>::parts;
+#pragma unroll
+    for (int sum = P - 1; sum >= 0; --sum)
+#pragma unroll
+        for (int i = sum; i >= 0; --i) {
+            const int p = sum - i;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                if constexpr (ModeInfo<MODE>::f16)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(vec8<f16x8, _Float16>(&x[i][8 * s]),
+                                                                 vec8<f16x8, _Float16>(bq[p][s]), acc, 0, 0, 0);
+                else
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vec8<bf16x8, __bf16>(&x[i][8 * s]),
+                                                                  vec8<bf16x8, __bf16>(bq[p][s]), acc, 0, 0, 0);
+            }
+        }
+}
+
+template <int MODE, int DIR>
+__global__ void __launch_bounds__(256)
+k_mfma64(Addr a, int64_t batch, QTab q)
+{
+    constexpr int T0 = ModeInfo<MODE>::target;
+    const int lane = threadIdx.x & 63;
+    const int h = lane >> 5, c = lane & 31;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
+    const float qscale = MODE == M_FP8 ? 1.0f / (float)(1 << kF8QShift) : 1.0f;
+    for (int64_t b = wave; b < batch; b += nwaves) {
+        // d[I][K][16]: lane (h, c) holds row 32 I + c, columns 32 K + 8 qq + 4 h .. +3
+        float d[2][2][16];
+        const gfloat* src = a.src(b);
+#pragma unroll
+        for (int I = 0; I < 2; ++I)
+#pragma unroll
+            for (int K = 0; K < 2; ++K)
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq) {
+                    const float4 v =
+                        *reinterpret_cast<const gfloat4*>(src + (32 * I + c) * 64 + 32 * K + 8 * qq + 4 * h);
+                    d[I][K][4 * qq] = v.x; d[I][K][4 * qq + 1] = v.y;
+                    d[I][K][4 * qq + 2] = v.z; d[I][K][4 * qq + 3] = v.w;
+                }
+        float m = 0.f;
+#pragma unroll
+        for (int I = 0; I < 2; ++I)
+#pragma unroll
+            for (int K = 0; K < 2; ++K)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) m = fmaxf(m, fabsf(d[I][K][r]));
+        m = lane_max<1, 2, 4, 8, 16, 32>(m);
+        int etot = scale_exponent<T0>(m);
+#pragma unroll
+        for (int I = 0; I < 2; ++I)
+#pragma unroll
+            for (int K = 0; K < 2; ++K)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) d[I][K][r] = ldexpf(d[I][K][r], -etot);
+        constexpr int npass = DIR == DCT2D_ROUNDTRIP ? 4 : 2;
+#pragma unroll
+        for (int ps = 0; ps < npass; ++ps) {
+            const bool inv = DIR == DCT2D_INVERSE || (DIR == DCT2D_ROUNDTRIP && ps >= 2);
+            f32x16 acc[2][2];
+#pragma unroll
+            for (int I = 0; I < 2; ++I)
+#pragma unroll
+                for (int J = 0; J < 2; ++J)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[I][J][r] = 0.f;
+#pragma unroll
+            for (int I = 0; I < 2; ++I)
+#pragma unroll
+                for (int K = 0; K < 2; ++K) {
+                    // A tile (I, K): pass 1 holds X(I, K) at d[I][K]; later passes hold the
+                    // previous accumulator tile (K, I), whose registers represent its transpose
+                    const float* at = ps == 0 ? d[I][K] : d[K][I];
+                    if constexpr (MODE == M_FP8) {
+#pragma unroll
+                        for (int J = 0; J < 2; ++J)
+#pragma unroll
+                            for (int s = 0; s < 2; ++s) {
+                                int lo = __builtin_amdgcn_cvt_pk_fp8_f32(at[8 * s + 0], at[8 * s + 1], 0, false);
+                                lo = __builtin_amdgcn_cvt_pk_fp8_f32(at[8 * s + 2], at[8 * s + 3], lo, true);
+                                int hi = __builtin_amdgcn_cvt_pk_fp8_f32(at[8 * s + 4], at[8 * s + 5], 0, false);
+                                hi = __builtin_amdgcn_cvt_pk_fp8_f32(at[8 * s + 6], at[8 * s + 7], hi, true);
+                                const long av = (long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+                                acc[I][J] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(
+                                    av, load_b64_f8<MODE>(q, inv, h, c, K, J, s), acc[I][J], 0, 0, 0);
+                            }
+                    } else {
+                        float x[3][16];
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            float pp[3];
+                            split<MODE>(at[r], pp);
+#pragma unroll
+                            for (int i = 0; i < ModeInfo<MODE>::parts; ++i) x[i][r] = pp[i];
+                        }
+#pragma unroll
+                        for (int J = 0; J < 2; ++J) {
+                            float bt[3][2][8];
+                            load_b64_tile<MODE>(bt, q, inv, h, c, K, J);
+                            tile_products<MODE>(acc[I][J], x, bt);
+                        }
+                    }
+                }
+#pragma unroll
+            for (int I = 0; I < 2; ++I)
+#pragma unroll
+                for (int J = 0; J < 2; ++J)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) d[I][J][r] = acc[I][J][r] * qscale;
+            if (ModeInfo<MODE>::rescale && ps + 1 < npass) {
+                float m2 = 0.f;
+#pragma unroll
+                for (int I = 0; I < 2; ++I)
+#pragma unroll
+                    for (int J = 0; J < 2; ++J)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) m2 = fmaxf(m2, fabsf(d[I][J][r]));
+                m2 = lane_max<1, 2, 4, 8, 16, 32>(m2);
+                const int e1 = scale_exponent<T0>(m2);
+                etot += e1;
+#pragma unroll
+                for (int I = 0; I < 2; ++I)
+#pragma unroll
+                    for (int J = 0; J < 2; ++J)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) d[I][J][r] = ldexpf(d[I][J][r], -e1);
+            }
+        }
+        // after an even number of passes the lane holds tile (I, J) of Y^T:
+        // row 32 J + c, columns 32 I + 8 qq + 4 h .. +3 of Y
+        gfloat* dst = a.dst(b);
+#pragma unroll
+        for (int I = 0; I < 2; ++I)
+#pragma unroll
+            for (int J = 0; J < 2; ++J)
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq)
+                    *reinterpret_cast<gfloat4*>(dst + (32 * J + c) * 64 + 32 * I + 8 * qq + 4 * h) =
+                        make_float4(ldexpf(d[I][J][4 * qq], etot), ldexpf(d[I][J][4 * qq + 1], etot),
+                                    ldexpf(d[I][J][4 * qq + 2], etot), ldexpf(d[I][J][4 * qq + 3], etot));
     }
 }
 
@@ -538,6 +732,16 @@ int go32(const DeviceTables* t, const Job& j)
 }
 
 template <int MODE, int DIR>
+int go64(const DeviceTables* t, const Job& j)
+{
+    const int64_t cap = (int64_t)t->num_cu * 16;
+    const int64_t waves = j.batch < cap ? j.batch : cap;
+    const unsigned grid = (unsigned)((waves + 3) / 4);
+    k_mfma64<MODE, DIR><<<grid, 256, 0, j.stream>>>(j.addr(), j.batch, qtab(t, 64));
+    return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
+}
+
+template <int MODE, int DIR>
 int go_unroll(const DeviceTables* t, const Job& j)
 {
     // variant = unroll choice: 0 -> 2 tiles per iteration, 1 -> 1, 2 -> 4
@@ -551,6 +755,8 @@ int go_unroll(const DeviceTables* t, const Job& j)
     case 32:
         return j.variant == 1 ? go32<MODE, DIR, 1>(t, j) : j.variant == 2 ? go32<MODE, DIR, 4>(t, j)
                                                                            : go32<MODE, DIR, 2>(t, j);
+    case 64:
+        return go64<MODE, DIR>(t, j);
     default:
         return DCT2D_ERR_PRECISION;
     }
@@ -571,10 +777,14 @@ int go_dir(const DeviceTables* t, const Job& j)
 int mfma_supported(int rows, int cols, int precision)
 {
     if (precision < DCT2D_SPLIT_BF16X3 || precision > DCT2D_FP8_E4M3) return 0;
-    return rows == cols && (rows == 8 || rows == 16 || rows == 32);
+    return rows == cols && (rows == 8 || rows == 16 || rows == 32 || rows == 64);
 }
 
-int mfma_variant_count(int rows, int cols, int, int precision) { return mfma_supported(rows, cols, precision) ? 3 : 0; }
+int mfma_variant_count(int rows, int cols, int, int precision)
+{
+    if (!mfma_supported(rows, cols, precision)) return 0;
+    return rows == 64 ? 1 : 3;
+}
 
 int launch_mfma(const DeviceTables* t, const Job& j, int precision)
 {

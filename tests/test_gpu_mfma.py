@@ -32,11 +32,11 @@ def _limit(prec, direction):
 
 
 @pytest.mark.parametrize("prec", ["bf16x6", "fp16x3", "bf16x3", "bf16", "fp16", "fp8"])
-@pytest.mark.parametrize("n", (8, 16, 32))
+@pytest.mark.parametrize("n", (8, 16, 32, 64))
 @pytest.mark.parametrize("direction", DIRS)
 def test_paths_normal_inputs(prec, n, direction):
     _lib()
-    batch = {8: 1003, 16: 517, 32: 131}[n]  # several waves plus a ragged tail
+    batch = {8: 1003, 16: 517, 32: 131, 64: 71}[n]  # several waves plus a ragged tail
     x = workloads.c3_normal(n, batch=batch, seed=99 + n).x
     y = run(x, direction, prec)
     e = errors(x, y, direction)
@@ -45,7 +45,7 @@ def test_paths_normal_inputs(prec, n, direction):
 
 
 @pytest.mark.parametrize("prec", GATED)
-@pytest.mark.parametrize("n", (8, 16, 32))
+@pytest.mark.parametrize("n", (8, 16, 32, 64))
 def test_gated_paths_extreme_blocks(prec, n):
     """Power-of-two scaling per block: 2^+-100, 1e30 and zero blocks meet the gate."""
     _lib()
@@ -99,9 +99,9 @@ def test_mfma_determinism_and_unsupported_sizes():
     dct = _lib()
     x = workloads.c3_normal(16, batch=100, seed=1).x
     assert np.array_equal(run(x, "forward", "bf16x6"), run(x, "forward", "bf16x6"))
-    t = torch.zeros((4, 64, 64), device="cuda")
+    t = torch.zeros((4, 128, 128), device="cuda")
     with pytest.raises(dct.DCT2DError):
-        dct.transform(t, None, "forward", "bf16x6")  # matrix paths exist for N <= 32 only
+        dct.transform(t, None, "forward", "bf16x6")  # matrix paths exist for N <= 64 only
     t = torch.zeros((4, 8, 16), device="cuda")
     with pytest.raises(dct.DCT2DError):
         dct.transform(t, None, "forward", "fp16x3")  # squares only
