@@ -257,7 +257,7 @@ k_wave(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* _
 constexpr int S128_P = 129;
 
 template <int DIR>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2) // two workgroups per CU: the LDS tile allows exactly two
 k_split128(Addr a, int64_t batch, const float2* __restrict__ tw_in)
 {
     constexpr int L = 128, H = 64, P = S128_P;

@@ -26,6 +26,8 @@
 // rescale again after pass 1.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace dct {
@@ -434,17 +436,100 @@ __device__ __forceinline__ f32x16 pass32(const float (&d)[16], const B32<MODE>& 
     return acc;
 }
 
+// B operands packed once per wavefront in the instruction's element type.
+template <int MODE>
+struct B32P {
+    typedef typename std::conditional<ModeInfo<MODE>::f16, f16x8, bf16x8>::type V;
+    V v[3][2];
+};
+
+template <int MODE>
+__device__ __forceinline__ B32P<MODE> pack_b32(const B32<MODE>& b)
+{
+    B32P<MODE> r;
+    typedef typename B32P<MODE>::V V;
+    typedef typename std::conditional<ModeInfo<MODE>::f16, _Float16, __bf16>::type E;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) r.v[p][s] = vec8<V, E>(b.c[p][s]);
+    return r;
+}
+
+template <int MODE>
+__device__ __forceinline__ f32x16 pass32p(const float (&d)[16], const B32P<MODE>& bq, const long (&b8)[2])
+{
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    if constexpr (MODE == M_FP8) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            int lo = __builtin_amdgcn_cvt_pk_fp8_f32(d[8 * s + 0], d[8 * s + 1], 0, false);
+            lo = __builtin_amdgcn_cvt_pk_fp8_f32(d[8 * s + 2], d[8 * s + 3], lo, true);
+            int hi = __builtin_amdgcn_cvt_pk_fp8_f32(d[8 * s + 4], d[8 * s + 5], 0, false);
+            hi = __builtin_amdgcn_cvt_pk_fp8_f32(d[8 * s + 6], d[8 * s + 7], hi, true);
+            const long a = (long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, b8[s], acc, 0, 0, 0);
+        }
+    } else {
+        typedef typename B32P<MODE>::V V;
+        typedef typename std::conditional<ModeInfo<MODE>::f16, _Float16, __bf16>::type E;
+        float x[3][16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            float pp[3];
+            split<MODE>(d[r], pp);
+#pragma unroll
+            for (int i = 0; i < ModeInfo<MODE>::parts; ++i) x[i][r] = pp[i];
+        }
+        constexpr int P = ModeInfo<MODE>::parts;
+#pragma unroll
+        for (int sum = P - 1; sum >= 0; --sum)
+#pragma unroll
+            for (int i = sum; i >= 0; --i) {
+                const int p = sum - i;
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    if constexpr (ModeInfo<MODE>::f16)
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(vec8<V, E>(&x[i][8 * s]), bq.v[p][s], acc, 0, 0,
+                                                                     0);
+                    else
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vec8<V, E>(&x[i][8 * s]), bq.v[p][s], acc, 0,
+                                                                      0, 0);
+                }
+            }
+    }
+    return acc;
+}
+
+// Each 4 KB block moves between HBM and registers through a per-wavefront LDS tile
+// (row pitch 36 floats): the global side is contiguous (lane l carries the l-th
+// 16-byte chunk of each 1 KB quarter), the register side is the MFMA layout (lane
+// (h, c): row c, columns 8 qq + 4 h .. +3), and the 36-float pitch keeps the 16-byte
+// LDS reads and writes of consecutive rows on distinct banks.
+constexpr int M32_P = 36;
+
+__device__ __forceinline__ void wave_lds_fence()
+{
+    // LDS traffic of one wavefront is processed in order; this only orders the compiler
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int MODE, int DIR, int UNROLL>
 __global__ void __launch_bounds__(256)
 k_mfma32(Addr a, int64_t batch, QTab q)
 {
     constexpr int T0 = ModeInfo<MODE>::target;
+    __shared__ float4 lds4[4 * UNROLL * 32 * M32_P / 4];
     const int lane = threadIdx.x & 63;
     const int h = lane >> 5, c = lane & 31;
+    float* wl = reinterpret_cast<float*>(lds4) + (threadIdx.x >> 6) * UNROLL * 32 * M32_P;
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
-    const B32<MODE> bf = load_b32<MODE>(q, false, h, c);
-    const B32<MODE> bi = load_b32<MODE>(q, true, h, c);
+    const B32P<MODE> bf = pack_b32<MODE>(load_b32<MODE>(q, false, h, c));
+    const B32P<MODE> bi = pack_b32<MODE>(load_b32<MODE>(q, true, h, c));
     long bf8[2] = {0, 0}, bi8[2] = {0, 0};
     if constexpr (MODE == M_FP8) {
         bf8[0] = load_b32_f8<MODE>(q, false, h, c, 0);
@@ -454,18 +539,32 @@ k_mfma32(Addr a, int64_t batch, QTab q)
     }
     const float qscale = MODE == M_FP8 ? 1.0f / (float)(1 << kF8QShift) : 1.0f;
     for (int64_t b0 = wave * UNROLL; b0 < batch; b0 += nwaves * UNROLL) {
-        float d[UNROLL][16];
+        // coalesced loads: chunk ch = 64 qq + lane of block u -> row ch / 8, columns 4 (ch % 8)
+        float4 g[UNROLL][4];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-            const int64_t b = b0 + u;
-            // lane (h, c): row c, columns 8q + 4h .. +3 for q = 0..3  (S = X^T in accumulator terms)
+        for (int u = 0; u < UNROLL; ++u)
 #pragma unroll
             for (int qq = 0; qq < 4; ++qq) {
-                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (b < batch) v = *reinterpret_cast<const gfloat4*>(a.src(b) + c * 32 + 8 * qq + 4 * h);
+                g[u][qq] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (b0 + u < batch) g[u][qq] = *reinterpret_cast<const gfloat4*>(a.src(b0 + u) + 4 * (64 * qq + lane));
+            }
+        wave_lds_fence();
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const int ch = 64 * qq + lane;
+                *reinterpret_cast<float4*>(wl + u * 32 * M32_P + (ch >> 3) * M32_P + 4 * (ch & 7)) = g[u][qq];
+            }
+        wave_lds_fence();
+        float d[UNROLL][16];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const float4 v = *reinterpret_cast<const float4*>(wl + u * 32 * M32_P + c * M32_P + 8 * qq + 4 * h);
                 d[u][4 * qq] = v.x; d[u][4 * qq + 1] = v.y; d[u][4 * qq + 2] = v.z; d[u][4 * qq + 3] = v.w;
             }
-        }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
             float m = 0.f;
@@ -479,7 +578,7 @@ k_mfma32(Addr a, int64_t batch, QTab q)
 #pragma unroll
             for (int ps = 0; ps < npass; ++ps) {
                 const bool inv = DIR == DCT2D_INVERSE || (DIR == DCT2D_ROUNDTRIP && ps >= 2);
-                const f32x16 acc = pass32<MODE>(d[u], inv ? bi : bf, inv ? bi8 : bf8);
+                const f32x16 acc = pass32p<MODE>(d[u], inv ? bi : bf, inv ? bi8 : bf8);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) d[u][r] = acc[r] * qscale;
                 if (ModeInfo<MODE>::rescale && ps + 1 < npass) {
@@ -493,15 +592,25 @@ k_mfma32(Addr a, int64_t batch, QTab q)
                     for (int r = 0; r < 16; ++r) d[u][r] = ldexpf(d[u][r], -e1);
                 }
             }
-            const int64_t b = b0 + u;
-            if (b < batch) {
 #pragma unroll
-                for (int qq = 0; qq < 4; ++qq)
-                    *reinterpret_cast<gfloat4*>(a.dst(b) + c * 32 + 8 * qq + 4 * h) =
-                        make_float4(ldexpf(d[u][4 * qq], etot), ldexpf(d[u][4 * qq + 1], etot),
-                                    ldexpf(d[u][4 * qq + 2], etot), ldexpf(d[u][4 * qq + 3], etot));
+            for (int qq = 0; qq < 4; ++qq)
+                *reinterpret_cast<float4*>(wl + u * 32 * M32_P + c * M32_P + 8 * qq + 4 * h) =
+                    make_float4(ldexpf(d[u][4 * qq], etot), ldexpf(d[u][4 * qq + 1], etot),
+                                ldexpf(d[u][4 * qq + 2], etot), ldexpf(d[u][4 * qq + 3], etot));
+        }
+        wave_lds_fence();
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            if (b0 + u >= batch) continue;
+            gfloat* dst = a.dst(b0 + u);
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                const int ch = 64 * qq + lane;
+                *reinterpret_cast<gfloat4*>(dst + 4 * ch) =
+                    *reinterpret_cast<const float4*>(wl + u * 32 * M32_P + (ch >> 3) * M32_P + 4 * (ch & 7));
             }
         }
+        wave_lds_fence();
     }
 }
 
