@@ -555,10 +555,16 @@ int launch_wave_dir(const DeviceTables* t, const Job& j)
 {
     using C = WaveCfg<H, W>;
     const int64_t ntiles = (j.batch + C::BPW - 1) / C::BPW;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wave<H, W, DIR>, 64, 0) != hipSuccess || per_cu < 1)
-        per_cu = 1;
-    const int64_t cap = (int64_t)t->num_cu * per_cu * 4;
+    int64_t cap;
+    if (j.variant == 3) {
+        cap = (int64_t)1 << 30; // one tile per workgroup (no grid-stride reuse)
+    } else {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wave<H, W, DIR>, 64, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        cap = (int64_t)t->num_cu * per_cu * 4;
+    }
     const unsigned grid = (unsigned)(ntiles < cap ? ntiles : cap);
     k_wave<H, W, DIR><<<grid, 64, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, H), tw_for(t, W));
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
@@ -738,14 +744,15 @@ int launch_fused(const DeviceTables* t, const Job& j)
 } // namespace
 
 // Variants (frozen per size by the policy table / autotuner):
-//   both axes <= 64:  0 wave-local fused, 1 LDS-staged fused, 2 two-pass
+//   both axes <= 64:  0 wave-local fused, 1 LDS-staged fused, 2 two-pass,
+//                     3 wave-local fused with one tile per workgroup
 //   128 x 128:        0 split fused (two wavefronts per transform), 1 LDS-staged fused, 2 two-pass
 //   other axes <=128: 0 LDS-staged fused, 1 two-pass
 //   256 x 256:        0 fused (rows in registers, columns in two LDS rounds), 1 two-pass
 //   other, an axis of 256: 0 two-pass
 int fp32_variant_count(int rows, int cols, int)
 {
-    if (rows <= 64 && cols <= 64) return 3;
+    if (rows <= 64 && cols <= 64) return 4;
     if (rows == 128 && cols == 128) return 3;
     if (rows <= 128 && cols <= 128) return 2;
     if (rows == 256 && cols == 256) return 2;
@@ -755,7 +762,7 @@ int fp32_variant_count(int rows, int cols, int)
 int launch_fp32(const DeviceTables* t, const Job& j)
 {
     if (j.rows <= 64 && j.cols <= 64) {
-        if (j.variant == 0) return launch_wave(t, j);
+        if (j.variant == 0 || j.variant == 3) return launch_wave(t, j);
         if (j.variant == 1) return launch_fused(t, j);
         return launch_two_pass(t, j);
     }

@@ -822,7 +822,8 @@ int go16(const DeviceTables* t, const Job& j)
     constexpr int BPT = N == 8 ? 4 : 1;
     const int64_t ntiles = (j.batch + BPT - 1) / BPT;
     const int64_t waves_needed = (ntiles + UNROLL - 1) / UNROLL;
-    const int64_t cap = (int64_t)t->num_cu * 32; // 8 waves per SIMD
+    // variant 3: one iteration per wavefront (no grid-stride reuse); otherwise 8 waves per SIMD
+    const int64_t cap = j.variant == 3 ? ((int64_t)1 << 32) : (int64_t)t->num_cu * 32;
     const int64_t waves = waves_needed < cap ? waves_needed : cap;
     const unsigned grid = (unsigned)((waves + 3) / 4);
     k_mfma16<N, MODE, DIR, UNROLL><<<grid, 256, 0, j.stream>>>(j.addr(), j.batch, qtab(t, N));
@@ -856,11 +857,13 @@ int go_unroll(const DeviceTables* t, const Job& j)
     // variant = unroll choice: 0 -> 2 tiles per iteration, 1 -> 1, 2 -> 4
     switch (j.rows) {
     case 8:
-        return j.variant == 1 ? go16<8, MODE, DIR, 1>(t, j) : j.variant == 2 ? go16<8, MODE, DIR, 4>(t, j)
-                                                                               : go16<8, MODE, DIR, 2>(t, j);
+        return j.variant == 1 || j.variant == 3 ? go16<8, MODE, DIR, 1>(t, j)
+               : j.variant == 2                 ? go16<8, MODE, DIR, 4>(t, j)
+                                                : go16<8, MODE, DIR, 2>(t, j);
     case 16:
-        return j.variant == 1 ? go16<16, MODE, DIR, 1>(t, j) : j.variant == 2 ? go16<16, MODE, DIR, 4>(t, j)
-                                                                                 : go16<16, MODE, DIR, 2>(t, j);
+        return j.variant == 1 || j.variant == 3 ? go16<16, MODE, DIR, 1>(t, j)
+               : j.variant == 2                 ? go16<16, MODE, DIR, 4>(t, j)
+                                                : go16<16, MODE, DIR, 2>(t, j);
     case 32:
         return j.variant == 1 ? go32<MODE, DIR, 1>(t, j) : j.variant == 2 ? go32<MODE, DIR, 4>(t, j)
                                                                            : go32<MODE, DIR, 2>(t, j);
@@ -892,7 +895,7 @@ int mfma_supported(int rows, int cols, int precision)
 int mfma_variant_count(int rows, int cols, int, int precision)
 {
     if (!mfma_supported(rows, cols, precision)) return 0;
-    return rows == 64 ? 1 : 3;
+    return rows == 64 ? 1 : rows == 32 ? 3 : 4; // unroll 2 / 1 / 4 (+ one-shot grid for 16x16 tiles)
 }
 
 int launch_mfma(const DeviceTables* t, const Job& j, int precision)
