@@ -58,6 +58,18 @@ inline bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 typedef DCT_GLOBAL float gfloat;
 typedef DCT_GLOBAL float4 gfloat4;
 
+// Marks a pointer that is the same in every lane of a wavefront as uniform, so its
+// arithmetic stays in scalar registers and memory instructions use a scalar base with
+// a 32-bit per-lane offset.  Only for values that really are wave-uniform.
+template <typename T>
+__device__ __forceinline__ T* uniform_ptr(T* p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (T*)(((uint64_t)hi << 32) | lo);
+}
+
 // ---- array addressing ---------------------------------------------------------------
 // Array b of a batch starts at in + in_idx[b] (indexed: ragged batches) or at
 // in + b * in_stride (strided batches); likewise for the output.  When a slot is

@@ -349,121 +349,434 @@ k_split128(Addr a, int64_t batch, const float2* __restrict__ tw_in)
     }
 }
 
-// Fused kernel for 256 x 256 arrays (256 KB, larger than LDS): one 256-thread workgroup
-// per array.  Thread t transforms row t in registers (a whole length-256 transform);
-// the column pass then runs in two rounds of 128 columns through a 256 x 128 LDS tile
-// (pitch 129).  In a round, column c is shared by two wavefronts as in k_split128:
-// role 0 handles the even half (DCT-II_128 / DCT-III_128), role 1 the odd half
-// (DCT-IV_128); for the inverse the two halves are recombined (a + b, a - b) through
-// LDS before a coalesced store (consecutive lanes = consecutive columns).  The second
-// 128 columns of a transformed row wait in the thread's own output row (re-read by the
-// same thread in the second round), which keeps the register footprint of the column
-// rounds free of them.
-//   forward:  rows (HBM -> regs) | 2 x [regs -> LDS -> column halves -> HBM]
-//   inverse:  rows (inverse, HBM -> regs) | 2 x [regs -> LDS -> halves -> LDS -> HBM]
-//   round trip: forward rows | 2 x [forward + inverse column halves -> HBM] | inverse
-//               rows (the column-inverted intermediate is re-read from the array's own
-//               memory after a workgroup barrier)
-constexpr int S256_P = 129;
+// Fused kernel for 256 x 256 arrays: one 512-thread workgroup per array, one workgroup
+// per CU.  Every length-256 transform is shared by two halves of the workgroup through
+// the top level of the even/odd recursion (dct1d.hpp), so each thread holds 128 values:
+// group E (wavefronts 0-3) takes the DCT-II_128 / DCT-III_128 half of every row
+// transform, group O (wavefronts 4-7) the DCT-IV_128 half.  The array (256 KB) is
+// larger than the LDS, which is used in three layouts, each holding half of it:
+//   column-half stage: rows 0..255, 128 columns, pitch 132;
+//   row-half stage:    128 rows, 256 columns, pitch 260;
+//   tile:              rows 0..255, 128 columns, pitch 129 (odd: conflict-free row
+//                      writes and column reads).
+// The stages move the array between HBM and LDS with coalesced 16-byte accesses (each
+// wavefront instruction covers whole 512-byte half-rows or 1 KB rows), in two windows
+// each way.  The second pass runs in two rounds through the tile, one per group;
+// inside a round, wavefronts with cr = 0 take the even half of each column transform
+// and cr = 1 the odd half.
+//   forward:    column halves in, rows (E: even outputs, O: odd outputs) | round E:
+//               E's outputs (the even columns) through the tile, column transforms |
+//               round O: the odd columns | coefficients out by row halves
+//   inverse:    row halves in, columns (E: even columns, O: odd columns; per column the
+//               halves a, b with Z[n] = a[n] + b[n], Z[255-n] = a[n] - b[n]) | round E:
+//               E's halves through the tile, each E thread inverts the even entries of
+//               one row (p) | round O: the odd entries (q) | out by column halves: E
+//               writes p, O adds q (left half, x[m] = p[m] + q[m]) or subtracts it
+//               (right half, x[255-m] = p[m] - q[m])
+//   round trip: in as the forward, rows | per round: forward + inverse column
+//               transforms in registers, then the inverse rows | out as the inverse.
+// Every (group, column half) pair runs its own straight-line path; the four paths
+// pass the same sequence of workgroup barriers (forward 12, inverse 14, round trip 18
+// per array).  The array is read whole before its first barrier and written after,
+// so in-place operation is safe.
+namespace s256 {
+constexpr int L = 256, H = 128, P = 129, CP = 132, RP = 260;
+constexpr int LDS_FLOATS = L * CP; // the largest layout (256 x 132 > 128 x 260 > 256 x 129)
+
+// A lane index made opaque at the start of each phase: the hundreds of LDS and array
+// offsets derived from it are then formed inside that phase, instead of being hoisted
+// to a point where they would all stay live.
+__device__ __forceinline__ int fresh(int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// Makes the lane index depend on an already read value, so the reads of the next
+// chunk of a phase cannot be issued before that value has arrived: bounds the number
+// of LDS reads in flight (and the registers they hold) to one chunk.
+__device__ __forceinline__ void after(int& idx, float dep)
+{
+    asm volatile("" : "+v"(idx) : "v"(dep));
+}
+
+__device__ __forceinline__ void syncs(int n)
+{
+    for (int k = 0; k < n; ++k) __syncthreads();
+}
+
+__device__ __forceinline__ const gfloat4* at4(const gfloat* base, uint32_t byte_off)
+{
+    return reinterpret_cast<const gfloat4*>(reinterpret_cast<const DCT_GLOBAL char*>(base) + byte_off);
+}
+__device__ __forceinline__ gfloat4* at4(gfloat* base, uint32_t byte_off)
+{
+    return reinterpret_cast<gfloat4*>(reinterpret_cast<DCT_GLOBAL char*>(base) + byte_off);
+}
+
+// ---- column-half stage: quadruple f = it * 512 + t (it < 16) is row f / 32, columns
+// 4 (f % 32) .. +3 of column half HF.  Byte offsets are 32-bit from the wave-uniform base.
+template <int HF>
+__device__ __forceinline__ void load_colhalf(const gfloat* src, int t, float (&q)[64])
+{
+    t = fresh(t);
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int f = it * 512 + t;
+        const float4 v = *at4(src, (uint32_t)((f >> 5) * 1024 + HF * 512 + (f & 31) * 16));
+        q[4 * it] = v.x; q[4 * it + 1] = v.y; q[4 * it + 2] = v.z; q[4 * it + 3] = v.w;
+    }
+}
+__device__ __forceinline__ void put_colhalf(float* T, int t, const float (&q)[64])
+{
+    t = fresh(t);
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int f = it * 512 + t;
+        *reinterpret_cast<float4*>(&T[(f >> 5) * CP + 4 * (f & 31)]) =
+            make_float4(q[4 * it], q[4 * it + 1], q[4 * it + 2], q[4 * it + 3]);
+    }
+}
+template <int HF>
+__device__ __forceinline__ void out_colhalf(gfloat* dst, const float* T, int t)
+{
+    t = fresh(t);
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int f = it * 512 + t;
+        *at4(dst, (uint32_t)((f >> 5) * 1024 + HF * 512 + (f & 31) * 16)) =
+            *reinterpret_cast<const float4*>(&T[(f >> 5) * CP + 4 * (f & 31)]);
+    }
+}
+
+// ---- row-half stage: quadruple f = it * 512 + t (it < 16) is row HF * 128 + f / 64,
+// columns 4 (f % 64) .. +3.
+template <int HF>
+__device__ __forceinline__ void load_rowhalf(const gfloat* src, int t, float (&q)[64])
+{
+    t = fresh(t);
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int f = it * 512 + t;
+        const float4 v = *at4(src, (uint32_t)((HF * 128 + (f >> 6)) * 1024 + (f & 63) * 16));
+        q[4 * it] = v.x; q[4 * it + 1] = v.y; q[4 * it + 2] = v.z; q[4 * it + 3] = v.w;
+    }
+}
+__device__ __forceinline__ void put_rowhalf(float* T, int t, const float (&q)[64])
+{
+    t = fresh(t);
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int f = it * 512 + t;
+        *reinterpret_cast<float4*>(&T[(f >> 6) * RP + 4 * (f & 63)]) =
+            make_float4(q[4 * it], q[4 * it + 1], q[4 * it + 2], q[4 * it + 3]);
+    }
+}
+template <int HF>
+__device__ __forceinline__ void out_rowhalf(gfloat* dst, const float* T, int t)
+{
+    t = fresh(t);
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+        const int f = it * 512 + t;
+        *at4(dst, (uint32_t)((HF * 128 + (f >> 6)) * 1024 + (f & 63) * 16)) =
+            *reinterpret_cast<const float4*>(&T[(f >> 6) * RP + 4 * (f & 63)]);
+    }
+}
+
+// ---- forward rows through the column-half stage: row i; group 0: u[n] = x[n] +
+// x[255-n] -> DCT-II_128 (even outputs), group 1: w[n] = x[n] - x[255-n] -> DCT-IV_128
+// (odd outputs).  Four barriers: left half in, read, right half in, read.
+template <int G>
+__device__ __forceinline__ void rows_fwd(const gfloat* src, float* T, int t, int i, float (&R)[H], twptr tw)
+{
+    float xl[H];
+    {
+        float qa[64], qb[64];
+        load_colhalf<0>(src, t, qa);
+        load_colhalf<1>(src, t, qb);
+        __syncthreads(); // earlier readers of the LDS are done
+        put_colhalf(T, t, qa);
+        __syncthreads();
+        int r = fresh(i);
+#pragma unroll
+        for (int j = 0; j < H / 4; ++j) {
+            const float4 a = *reinterpret_cast<const float4*>(&T[r * CP + 4 * j]);
+            xl[4 * j] = a.x; xl[4 * j + 1] = a.y; xl[4 * j + 2] = a.z; xl[4 * j + 3] = a.w;
+            if (j % 8 == 7) after(r, a.w);
+        }
+        __syncthreads();
+        put_colhalf(T, t, qb);
+        __syncthreads();
+    }
+    float v[H];
+    int r = fresh(i);
+#pragma unroll
+    for (int j = 0; j < H / 4; ++j) {
+        // stage column 124 - 4j .. 127 - 4j holds x[252 - 4j .. 255 - 4j]
+        const float4 b = *reinterpret_cast<const float4*>(&T[r * CP + H - 4 - 4 * j]);
+        const float xh[4] = {b.w, b.z, b.y, b.x}; // x[255 - (4j + q)]
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[4 * j + q] = G == 0 ? xl[4 * j + q] + xh[q] : xl[4 * j + q] - xh[q];
+        if (j % 8 == 7) after(r, v[4 * j + 3]);
+    }
+    if constexpr (G == 0) dct2_rec<L, H>(v, R, tw); else dct4_scaled<L, H>(v, R, tw);
+}
+
+// ---- inverse columns through the row-half stage: column 2 cc + G; CR 0: even
+// coefficient rows -> DCT-III_128 (a), CR 1: odd coefficient rows -> DCT-IV_128 (b).
+// Four barriers, as rows_fwd.
+template <int G, int CR>
+__device__ __forceinline__ void cols_inv(const gfloat* src, float* T, int t, int cc, float (&R)[H], twptr tw)
+{
+    float v[H];
+    {
+        float qa[64], qb[64];
+        load_rowhalf<0>(src, t, qa);
+        load_rowhalf<1>(src, t, qb);
+        __syncthreads();
+        put_rowhalf(T, t, qa);
+        __syncthreads();
+        int c = fresh(cc);
+#pragma unroll
+        for (int k = 0; k < H / 2; ++k) {
+            v[k] = T[(2 * k + CR) * RP + 2 * c + G];
+            if (k % 32 == 31) after(c, v[k]);
+        }
+        __syncthreads();
+        put_rowhalf(T, t, qb);
+        __syncthreads();
+    }
+    int c = fresh(cc);
+#pragma unroll
+    for (int k = H / 2; k < H; ++k) {
+        v[k] = T[(2 * k + CR - H) * RP + 2 * c + G];
+        if (k % 32 == 31) after(c, v[k]);
+    }
+    if constexpr (CR == 0) dct3_rec<L, H>(v, R, tw); else dct4_scaled<L, H>(v, R, tw);
+}
+
+// Row i of the tile <- the thread's 128 values.
+__device__ __forceinline__ void put_row(float* T, int i, const float (&R)[H])
+{
+    i = fresh(i);
+#pragma unroll
+    for (int k = 0; k < H; ++k) T[i * P + k] = R[k];
+}
+
+// Forward transform of tile column cc (256 values down the tile rows): CR 0 -> even
+// coefficients (DCT-II_128 of u), CR 1 -> odd coefficients (DCT-IV_128 of w).
+template <int CR>
+__device__ __forceinline__ void col_fwd(const float* T, int cc, float (&o)[H], twptr tw)
+{
+    cc = fresh(cc);
+    float v[H];
+#pragma unroll
+    for (int n = 0; n < H; ++n) {
+        const float xl = T[n * P + cc], xh = T[(L - 1 - n) * P + cc];
+        v[n] = CR == 0 ? xl + xh : xl - xh;
+        if (n % 32 == 31) after(cc, v[n]);
+    }
+    if constexpr (CR == 0) dct2_rec<L, H>(v, o, tw); else dct4_scaled<L, H>(v, o, tw);
+}
+
+// Inverse of the same column half: CR 0: DCT-III_128 of the even coefficients (a),
+// CR 1: DCT-IV_128 of the odd coefficients (b).
+template <int CR>
+__device__ __forceinline__ void col_inv(const float (&o)[H], float (&R)[H], twptr tw)
+{
+    if constexpr (CR == 0) dct3_rec<L, H>(o, R, tw); else dct4_scaled<L, H>(o, R, tw);
+}
+
+// Column halves into the tile: rows 0..127 hold a, rows 128..255 hold b (column cc).
+template <int CR>
+__device__ __forceinline__ void put_halves(float* T, int cc, const float (&R)[H])
+{
+    cc = fresh(cc);
+#pragma unroll
+    for (int n = 0; n < H; ++n) T[(CR * H + n) * P + cc] = R[n];
+}
+
+// Inverse transform of the entries of row i held in the tile as column halves:
+// Z[i][.] = a[r] + b[r] (i < 128, r = i) or a[r] - b[r] (r = 255 - i).  Group 0 has
+// the even entries (DCT-III_128), group 1 the odd entries (DCT-IV_128).
+template <int G>
+__device__ __forceinline__ void row_inv(const float* T, int i, float (&R)[H], twptr tw)
+{
+    i = fresh(i);
+    const bool top = i < H;
+    int r = top ? i : L - 1 - i;
+    const float sg = top ? 1.f : -1.f; // exact: one rounding, as a +- b
+    float o[H];
+#pragma unroll
+    for (int c = 0; c < H; ++c) {
+        o[c] = __builtin_fmaf(sg, T[(H + r) * P + c], T[r * P + c]);
+        if (c % 32 == 31) after(r, o[c]);
+    }
+    if constexpr (G == 0) dct3_rec<L, H>(o, R, tw); else dct4_scaled<L, H>(o, R, tw);
+}
+
+// ---- forward output: coefficient rows 2k + CR (k in half HF of 0..127) of column
+// 2 cc + G into the row-half stage, then out.  Four barriers with the stage windows.
+template <int G, int CR>
+__device__ __forceinline__ void coefs_out(gfloat* dst, float* T, int t, int cc, const float (&o)[H])
+{
+    {
+        const int c = fresh(cc);
+#pragma unroll
+        for (int k = 0; k < H / 2; ++k) T[(2 * k + CR) * RP + 2 * c + G] = o[k];
+    }
+    __syncthreads();
+    out_rowhalf<0>(dst, T, t);
+    __syncthreads();
+    {
+        const int c = fresh(cc);
+#pragma unroll
+        for (int k = H / 2; k < H; ++k) T[(2 * k + CR - H) * RP + 2 * c + G] = o[k];
+    }
+    __syncthreads();
+    out_rowhalf<1>(dst, T, t);
+}
+
+// ---- inverse output by column halves: x[i][m] = p[m] + q[m] (left), x[i][255-m] =
+// p[m] - q[m] (right, stage column 127 - m); group 0 writes p, then group 1 adds or
+// subtracts q.  Five barriers.
+template <int G>
+__device__ __forceinline__ void rows_out(gfloat* dst, float* T, int t, int i, const float (&R)[H])
+{
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+        const int r = fresh(i);
+        if (G == 0) {
+#pragma unroll
+            for (int j = 0; j < H / 4; ++j) {
+                float4* d = reinterpret_cast<float4*>(&T[r * CP + (hf == 0 ? 4 * j : H - 4 - 4 * j)]);
+                *d = hf == 0 ? make_float4(R[4 * j], R[4 * j + 1], R[4 * j + 2], R[4 * j + 3])
+                             : make_float4(R[4 * j + 3], R[4 * j + 2], R[4 * j + 1], R[4 * j]);
+            }
+        }
+        __syncthreads();
+        if (G == 1) {
+#pragma unroll
+            for (int j = 0; j < H / 4; ++j) {
+                float4* d = reinterpret_cast<float4*>(&T[r * CP + (hf == 0 ? 4 * j : H - 4 - 4 * j)]);
+                float4 s = *d;
+                if (hf == 0) {
+                    s.x += R[4 * j]; s.y += R[4 * j + 1]; s.z += R[4 * j + 2]; s.w += R[4 * j + 3];
+                } else {
+                    s.w -= R[4 * j]; s.z -= R[4 * j + 1]; s.y -= R[4 * j + 2]; s.x -= R[4 * j + 3];
+                }
+                *d = s;
+            }
+        }
+        __syncthreads();
+        if (hf == 0) out_colhalf<0>(dst, T, t); else out_colhalf<1>(dst, T, t);
+        if (hf == 0) __syncthreads();
+    }
+}
+
+// One (group, column half) path of one array.
+template <int DIR, int G, int CR>
+__device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, int t, int i, int cc, twptr tw)
+{
+    float R[H];
+    if constexpr (DIR == DCT2D_FORWARD) {
+        rows_fwd<G>(src, T, t, i, R, tw);
+        float o[H];
+        tw_fence(tw);
+        if constexpr (G == 0) {
+            __syncthreads(); // stage reads done
+            put_row(T, i, R);
+            __syncthreads();
+            col_fwd<CR>(T, cc, o, tw);
+            syncs(3); // round O
+        } else {
+            syncs(3); // round E
+            put_row(T, i, R);
+            __syncthreads();
+            col_fwd<CR>(T, cc, o, tw);
+            __syncthreads();
+        }
+        coefs_out<G, CR>(dst, T, t, cc, o);
+    } else {
+        if constexpr (DIR == DCT2D_INVERSE) {
+            cols_inv<G, CR>(src, T, t, cc, R, tw);
+            tw_fence(tw);
+            if constexpr (G == 0) {
+                __syncthreads();
+                put_halves<CR>(T, cc, R);
+                __syncthreads();
+                row_inv<0>(T, i, R, tw); // p
+                syncs(3);                // round O
+            } else {
+                syncs(3); // round E
+                put_halves<CR>(T, cc, R);
+                __syncthreads();
+                row_inv<1>(T, i, R, tw); // q
+                __syncthreads();
+            }
+        } else {
+            rows_fwd<G>(src, T, t, i, R, tw);
+            tw_fence(tw);
+            if constexpr (G == 0) {
+                __syncthreads();
+                put_row(T, i, R);
+                __syncthreads();
+                {
+                    float o[H];
+                    col_fwd<CR>(T, cc, o, tw);
+                    tw_fence(tw);
+                    col_inv<CR>(o, R, tw);
+                }
+                __syncthreads();
+                put_halves<CR>(T, cc, R);
+                __syncthreads();
+                row_inv<0>(T, i, R, tw); // p
+                syncs(5);                // round O
+            } else {
+                syncs(5); // round E
+                put_row(T, i, R);
+                __syncthreads();
+                {
+                    float o[H];
+                    col_fwd<CR>(T, cc, o, tw);
+                    tw_fence(tw);
+                    col_inv<CR>(o, R, tw);
+                }
+                __syncthreads();
+                put_halves<CR>(T, cc, R);
+                __syncthreads();
+                row_inv<1>(T, i, R, tw); // q
+                __syncthreads();
+            }
+        }
+        rows_out<G>(dst, T, t, i, R);
+    }
+}
+} // namespace s256
 
 template <int DIR>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512, 1)
 k_split256(Addr a, int64_t batch, const float2* __restrict__ tw_in)
 {
-    constexpr int L = 256, H = 128, P = S256_P;
-    __shared__ float T[L * P];
+    using namespace s256;
+    __shared__ float4 T4[LDS_FLOATS / 4];
+    float* const T = reinterpret_cast<float*>(T4);
     const int t = threadIdx.x;
-    const int role = t >> 7; // column passes: 0 even half, 1 odd half (uniform per wavefront)
-    const int c = t & 127;   // column within the round
+    const int g = __builtin_amdgcn_readfirstlane(t >> 8);        // group, uniform per wavefront
+    const int cr = __builtin_amdgcn_readfirstlane((t >> 7) & 1); // column half, uniform per wavefront
+    const int i = t & 255;  // row of the row phases
+    const int cc = t & 127; // column slot of the column phases: column 2 cc + group
     for (int64_t blk = blockIdx.x; blk < batch; blk += gridDim.x) {
-        twptr tw = per_iteration(tw_in);
-        const gfloat* src = a.src(blk);
-        gfloat* dst = a.dst(blk);
-        float y[L];
-        {
-            const gfloat* row = src + (int64_t)t * L;
-#pragma unroll
-            for (int j = 0; j < L / 4; ++j) {
-                const float4 q = *reinterpret_cast<const gfloat4*>(row + 4 * j);
-                y[4 * j] = q.x; y[4 * j + 1] = q.y; y[4 * j + 2] = q.z; y[4 * j + 3] = q.w;
-            }
-        }
-        if (DIR == DCT2D_INVERSE) dct3_ortho<L>(y, tw); else dct2_ortho<L>(y, tw);
-        // Park the second half of the transformed row in this thread's own output row
-        // (already consumed as input by this same thread) until the second round, so no
-        // thread keeps 128 extra values live through the first column round.
-        {
-            gfloat* prow = dst + (int64_t)t * L + H;
-#pragma unroll
-            for (int j = 0; j < H / 4; ++j)
-                *reinterpret_cast<gfloat4*>(prow + 4 * j) =
-                    make_float4(y[H + 4 * j], y[H + 4 * j + 1], y[H + 4 * j + 2], y[H + 4 * j + 3]);
-        }
-#pragma unroll
-        for (int round = 0; round < 2; ++round) {
-            asm volatile("" : "+s"(tw));
-            if (round == 0) {
-#pragma unroll
-                for (int j = 0; j < H; ++j) T[t * P + j] = y[j];
-            } else {
-                const gfloat* prow = dst + (int64_t)t * L + H;
-#pragma unroll
-                for (int j = 0; j < H / 4; ++j) {
-                    const float4 q = *reinterpret_cast<const gfloat4*>(prow + 4 * j);
-                    T[t * P + 4 * j] = q.x; T[t * P + 4 * j + 1] = q.y;
-                    T[t * P + 4 * j + 2] = q.z; T[t * P + 4 * j + 3] = q.w;
-                }
-            }
-            __syncthreads();
-            float v[H], o[H];
-            if (DIR != DCT2D_INVERSE) {
-#pragma unroll
-                for (int n = 0; n < H; ++n) {
-                    const float xl = T[n * P + c], xh = T[(L - 1 - n) * P + c];
-                    v[n] = role == 0 ? xl + xh : xl - xh;
-                }
-                if (role == 0) dct2_rec<L, H>(v, o, tw); else dct4_scaled<L, H>(v, o, tw);
-                if (DIR == DCT2D_FORWARD) {
-#pragma unroll
-                    for (int k = 0; k < H; ++k) dst[(int64_t)(2 * k + role) * L + H * round + c] = o[k];
-                    __syncthreads(); // the next round overwrites the tile
-                    continue;
-                }
-                asm volatile("" : "+s"(tw));
-                if (role == 0) dct3_rec<L, H>(o, v, tw); else dct4_scaled<L, H>(o, v, tw);
-            } else {
-#pragma unroll
-                for (int k = 0; k < H; ++k) o[k] = T[(2 * k + role) * P + c];
-                if (role == 0) dct3_rec<L, H>(o, v, tw); else dct4_scaled<L, H>(o, v, tw);
-            }
-            __syncthreads(); // every column read before the halves overwrite the tile
-#pragma unroll
-            for (int n = 0; n < H; ++n) T[(role * H + n) * P + c] = v[n];
-            __syncthreads();
-            // recombine: column value x[n] = a[n] + b[n], x[255-n] = a[n] - b[n]
-#pragma unroll
-            for (int n = 0; n < H; ++n) {
-                const float av = T[n * P + c], bv = T[(H + n) * P + c];
-                const int r = role == 0 ? n : L - 1 - n;
-                dst[(int64_t)r * L + H * round + c] = role == 0 ? av + bv : av - bv;
-            }
-            __syncthreads();
-        }
-        if (DIR == DCT2D_ROUNDTRIP) {
-            // inverse rows on the column-inverted intermediate written above by this workgroup
-            const gfloat* row = dst + (int64_t)t * L;
-#pragma unroll
-            for (int j = 0; j < L / 4; ++j) {
-                const float4 q = *reinterpret_cast<const gfloat4*>(row + 4 * j);
-                y[4 * j] = q.x; y[4 * j + 1] = q.y; y[4 * j + 2] = q.z; y[4 * j + 3] = q.w;
-            }
-            asm volatile("" : "+s"(tw));
-            dct3_ortho<L>(y, tw);
-            gfloat* orow = dst + (int64_t)t * L;
-#pragma unroll
-            for (int j = 0; j < L / 4; ++j)
-                *reinterpret_cast<gfloat4*>(orow + 4 * j) = make_float4(y[4 * j], y[4 * j + 1], y[4 * j + 2], y[4 * j + 3]);
-            __syncthreads();
+        const twptr tw = per_iteration(tw_in);
+        const gfloat* src = uniform_ptr(a.src(blk));
+        gfloat* dst = uniform_ptr(a.dst(blk));
+        if (g == 0) {
+            if (cr == 0) path<DIR, 0, 0>(src, dst, T, t, i, cc, tw);
+            else path<DIR, 0, 1>(src, dst, T, t, i, cc, tw);
+        } else {
+            if (cr == 0) path<DIR, 1, 0>(src, dst, T, t, i, cc, tw);
+            else path<DIR, 1, 1>(src, dst, T, t, i, cc, tw);
         }
     }
 }
@@ -628,11 +941,12 @@ template <int DIR>
 int launch_split256_dir(const DeviceTables* t, const Job& j)
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_split256<DIR>, 256, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_split256<DIR>, 512, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    const int64_t cap = (int64_t)t->num_cu * per_cu * 4;
+    // variant 0: one resident workgroup per CU looping over arrays; variant 2: one array per workgroup
+    const int64_t cap = j.variant == 2 ? ((int64_t)1 << 31) - 1 : (int64_t)t->num_cu * per_cu;
     const unsigned grid = (unsigned)(j.batch < cap ? j.batch : cap);
-    k_split256<DIR><<<grid, 256, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, 256));
+    k_split256<DIR><<<grid, 512, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, 256));
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
 }
 
@@ -748,14 +1062,16 @@ int launch_fused(const DeviceTables* t, const Job& j)
 //                     3 wave-local fused with one tile per workgroup
 //   128 x 128:        0 split fused (two wavefronts per transform), 1 LDS-staged fused, 2 two-pass
 //   other axes <=128: 0 LDS-staged fused, 1 two-pass
-//   256 x 256:        0 fused (rows in registers, columns in two LDS rounds), 1 two-pass
+//   256 x 256:        0 split fused (two groups of wavefronts, two LDS rounds), one
+//                     resident workgroup per CU; 1 two-pass; 2 split fused, one array
+//                     per workgroup
 //   other, an axis of 256: 0 two-pass
 int fp32_variant_count(int rows, int cols, int)
 {
     if (rows <= 64 && cols <= 64) return 4;
     if (rows == 128 && cols == 128) return 3;
     if (rows <= 128 && cols <= 128) return 2;
-    if (rows == 256 && cols == 256) return 2;
+    if (rows == 256 && cols == 256) return 3;
     return 1;
 }
 
@@ -772,7 +1088,7 @@ int launch_fp32(const DeviceTables* t, const Job& j)
         return launch_two_pass(t, j);
     }
     if (j.rows <= 128 && j.cols <= 128 && j.variant == 0) return launch_fused(t, j);
-    if (j.rows == 256 && j.cols == 256 && j.variant == 0) return launch_split256(t, j);
+    if (j.rows == 256 && j.cols == 256 && j.variant != 1) return launch_split256(t, j);
     return launch_two_pass(t, j);
 }
 
