@@ -19,7 +19,8 @@ namespace {
 
 constexpr int kNumPrec = 8;
 
-// Frozen variant table: index [log2 rows - 3][log2 cols - 3][dir][precision]; -1 = default 0.
+// Frozen variant table: index [log2 rows - 3][log2 cols - 3][dir][precision]; starts from the
+// per-size defaults (the variants measured fastest on MI355X), overridable by the tuner.
 std::mutex g_policy_mu;
 int g_variant[6][6][3][kNumPrec];
 bool g_policy_ready = false;
@@ -27,10 +28,11 @@ bool g_policy_ready = false;
 void policy_init_locked()
 {
     if (g_policy_ready) return;
-    for (auto& a : g_variant)
-        for (auto& b : a)
-            for (auto& c : b)
-                for (int& v : c) v = 0;
+    for (int r = 0; r < 6; ++r)
+        for (int c = 0; c < 6; ++c)
+            for (int d = 0; d < 3; ++d)
+                for (int p = 0; p < kNumPrec; ++p)
+                    g_variant[r][c][d][p] = p == DCT2D_FP32 ? fp32_default_variant(8 << r, 8 << c, d) : 0;
     g_policy_ready = true;
 }
 

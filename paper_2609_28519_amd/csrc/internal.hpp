@@ -123,6 +123,7 @@ int launch_dense_axis(const Addr& a, int64_t count, int rows, int cols, bool col
 
 int launch_fp32(const DeviceTables* t, const Job& j);
 int fp32_variant_count(int rows, int cols, int dir);
+int fp32_default_variant(int rows, int cols, int dir);
 
 int launch_mfma(const DeviceTables* t, const Job& j, int precision);
 int mfma_supported(int rows, int cols, int precision);

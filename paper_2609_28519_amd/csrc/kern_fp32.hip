@@ -256,12 +256,16 @@ k_wave(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* _
 //   round trip: forward rows | forward + inverse columns in registers | inverse rows
 constexpr int S128_P = 129;
 
-template <int DIR>
+// STAGE: the forward rows come from an LDS copy of the array (row pitch 132) filled with
+// coalesced 16-byte loads (each wavefront instruction covers two whole rows) instead of
+// each thread reading its own row from HBM.
+template <int DIR, bool STAGE>
 __global__ void __launch_bounds__(256, 2) // two workgroups per CU: the LDS tile allows exactly two
 k_split128(Addr a, int64_t batch, const float2* __restrict__ tw_in)
 {
-    constexpr int L = 128, H = 64, P = S128_P;
-    __shared__ float T[L * P];
+    constexpr int L = 128, H = 64, P = S128_P, SP = 132;
+    __shared__ float4 T4[(STAGE ? L * SP : L * P) / 4];
+    float* const T = reinterpret_cast<float*>(T4);
     const int t = threadIdx.x;
     const int role = t >> 7;       // 0: even half, 1: odd half (uniform per wavefront)
     const int idx = t & 127;       // row or column handled by this thread
@@ -271,16 +275,44 @@ k_split128(Addr a, int64_t batch, const float2* __restrict__ tw_in)
         gfloat* dst = a.dst(blk);
         float v[H], o[H];
         if (DIR != DCT2D_INVERSE) {
-            // ---- forward rows: row idx from HBM --------------------------------------
-            const gfloat* row = src + (int64_t)idx * L;
+            // ---- forward rows: row idx ------------------------------------------------
+            if (STAGE) {
+                // (the previous array's last LDS reads precede its final barrier)
+                const DCT_GLOBAL char* sb = reinterpret_cast<const DCT_GLOBAL char*>(uniform_ptr(src));
+                float q[64];
 #pragma unroll
-            for (int j = 0; j < H / 4; ++j) {
-                const float4 lo = *reinterpret_cast<const gfloat4*>(row + 4 * j);
-                const float4 hi = *reinterpret_cast<const gfloat4*>(row + L - 4 - 4 * j);
-                const float xl[4] = {lo.x, lo.y, lo.z, lo.w};
-                const float xh[4] = {hi.w, hi.z, hi.y, hi.x}; // x[127 - (4j + i)]
+                for (int it = 0; it < 16; ++it) {
+                    const float4 w = *reinterpret_cast<const gfloat4*>(sb + (uint32_t)((it * 256 + t) * 16));
+                    q[4 * it] = w.x; q[4 * it + 1] = w.y; q[4 * it + 2] = w.z; q[4 * it + 3] = w.w;
+                }
 #pragma unroll
-                for (int i = 0; i < 4; ++i) v[4 * j + i] = role == 0 ? xl[i] + xh[i] : xl[i] - xh[i];
+                for (int it = 0; it < 16; ++it) {
+                    const int f = it * 256 + t; // row f / 32, columns 4 (f % 32) .. +3
+                    *reinterpret_cast<float4*>(&T[(f >> 5) * SP + 4 * (f & 31)]) =
+                        make_float4(q[4 * it], q[4 * it + 1], q[4 * it + 2], q[4 * it + 3]);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < H / 4; ++j) {
+                    const float4 lo = *reinterpret_cast<const float4*>(&T[idx * SP + 4 * j]);
+                    const float4 hi = *reinterpret_cast<const float4*>(&T[idx * SP + L - 4 - 4 * j]);
+                    const float xl[4] = {lo.x, lo.y, lo.z, lo.w};
+                    const float xh[4] = {hi.w, hi.z, hi.y, hi.x}; // x[127 - (4j + i)]
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[4 * j + i] = role == 0 ? xl[i] + xh[i] : xl[i] - xh[i];
+                }
+                __syncthreads(); // the staged copy is read before the tile overwrites it
+            } else {
+                const gfloat* row = src + (int64_t)idx * L;
+#pragma unroll
+                for (int j = 0; j < H / 4; ++j) {
+                    const float4 lo = *reinterpret_cast<const gfloat4*>(row + 4 * j);
+                    const float4 hi = *reinterpret_cast<const gfloat4*>(row + L - 4 - 4 * j);
+                    const float xl[4] = {lo.x, lo.y, lo.z, lo.w};
+                    const float xh[4] = {hi.w, hi.z, hi.y, hi.x}; // x[127 - (4j + i)]
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[4 * j + i] = role == 0 ? xl[i] + xh[i] : xl[i] - xh[i];
+                }
             }
             if (role == 0) dct2_rec<L, H>(v, o, tw); else dct4_scaled<L, H>(v, o, tw);
 #pragma unroll
@@ -383,13 +415,17 @@ namespace s256 {
 constexpr int L = 256, H = 128, P = 129, CP = 132, RP = 260;
 constexpr int LDS_FLOATS = L * CP; // the largest layout (256 x 132 > 128 x 260 > 256 x 129)
 
-// A lane index made opaque at the start of each phase: the hundreds of LDS and array
-// offsets derived from it are then formed inside that phase, instead of being hoisted
-// to a point where they would all stay live.
-__device__ __forceinline__ int fresh(int v)
+// The thread index, recomputed from the lane count (two ALU instructions) in every
+// phase that needs it rather than held in a register for the whole kernel: under the
+// register pressure of the 128-value transforms a long-lived index would be spilled,
+// and every spill reload waits for all outstanding HBM stores of the wavefront.  The
+// asm keeps each recomputation (and the offsets derived from it) inside its phase.
+// `wid` is the wavefront index (wave-uniform, a scalar register).
+__device__ __forceinline__ int lane_t(int wid)
 {
-    asm volatile("" : "+v"(v));
-    return v;
+    int l;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+    return wid * 64 + l;
 }
 
 // Makes the lane index depend on an already read value, so the reads of the next
@@ -414,22 +450,31 @@ __device__ __forceinline__ gfloat4* at4(gfloat* base, uint32_t byte_off)
     return reinterpret_cast<gfloat4*>(reinterpret_cast<DCT_GLOBAL char*>(base) + byte_off);
 }
 
-// ---- column-half stage: quadruple f = it * 512 + t (it < 16) is row f / 32, columns
-// 4 (f % 32) .. +3 of column half HF.  Byte offsets are 32-bit from the wave-uniform base.
+// ---- column-half stage: the outer half (array columns 0..63 and 192..255, at stage
+// columns 0..63 and 64..127) or the inner half (array columns 64..191).  Either way stage
+// row r holds, at columns c and 127 - c (c < 64), the mirrored pair of array columns
+// (k, 255 - k) with k = c (outer) or 64 + c (inner), so each half feeds 64 even/odd
+// butterflies per row.  Quadruple f = it * 512 + t (it < 16) is row f / 32, stage
+// columns 4 (f % 32) .. +3.  Byte offsets are 32-bit from the wave-uniform base.
 template <int HF>
-__device__ __forceinline__ void load_colhalf(const gfloat* src, int t, float (&q)[64])
+__device__ __forceinline__ uint32_t colhalf_off(int f)
 {
-    t = fresh(t);
+    const int c4 = f & 31;
+    return (uint32_t)((f >> 5) * 1024 + (HF == 0 ? (c4 < 16 ? 16 * c4 : 16 * c4 + 512) : 256 + 16 * c4));
+}
+template <int HF>
+__device__ __forceinline__ void load_colhalf(const gfloat* src, int wid, float (&q)[64])
+{
+    const int t = lane_t(wid);
 #pragma unroll
     for (int it = 0; it < 16; ++it) {
-        const int f = it * 512 + t;
-        const float4 v = *at4(src, (uint32_t)((f >> 5) * 1024 + HF * 512 + (f & 31) * 16));
+        const float4 v = *at4(src, colhalf_off<HF>(it * 512 + t));
         q[4 * it] = v.x; q[4 * it + 1] = v.y; q[4 * it + 2] = v.z; q[4 * it + 3] = v.w;
     }
 }
-__device__ __forceinline__ void put_colhalf(float* T, int t, const float (&q)[64])
+__device__ __forceinline__ void put_colhalf(float* T, int wid, const float (&q)[64])
 {
-    t = fresh(t);
+    const int t = lane_t(wid);
 #pragma unroll
     for (int it = 0; it < 16; ++it) {
         const int f = it * 512 + t;
@@ -438,23 +483,22 @@ __device__ __forceinline__ void put_colhalf(float* T, int t, const float (&q)[64
     }
 }
 template <int HF>
-__device__ __forceinline__ void out_colhalf(gfloat* dst, const float* T, int t)
+__device__ __forceinline__ void out_colhalf(gfloat* dst, const float* T, int wid)
 {
-    t = fresh(t);
+    const int t = lane_t(wid);
 #pragma unroll
     for (int it = 0; it < 16; ++it) {
         const int f = it * 512 + t;
-        *at4(dst, (uint32_t)((f >> 5) * 1024 + HF * 512 + (f & 31) * 16)) =
-            *reinterpret_cast<const float4*>(&T[(f >> 5) * CP + 4 * (f & 31)]);
+        *at4(dst, colhalf_off<HF>(f)) = *reinterpret_cast<const float4*>(&T[(f >> 5) * CP + 4 * (f & 31)]);
     }
 }
 
 // ---- row-half stage: quadruple f = it * 512 + t (it < 16) is row HF * 128 + f / 64,
 // columns 4 (f % 64) .. +3.
 template <int HF>
-__device__ __forceinline__ void load_rowhalf(const gfloat* src, int t, float (&q)[64])
+__device__ __forceinline__ void load_rowhalf(const gfloat* src, int wid, float (&q)[64])
 {
-    t = fresh(t);
+    const int t = lane_t(wid);
 #pragma unroll
     for (int it = 0; it < 16; ++it) {
         const int f = it * 512 + t;
@@ -462,9 +506,9 @@ __device__ __forceinline__ void load_rowhalf(const gfloat* src, int t, float (&q
         q[4 * it] = v.x; q[4 * it + 1] = v.y; q[4 * it + 2] = v.z; q[4 * it + 3] = v.w;
     }
 }
-__device__ __forceinline__ void put_rowhalf(float* T, int t, const float (&q)[64])
+__device__ __forceinline__ void put_rowhalf(float* T, int wid, const float (&q)[64])
 {
-    t = fresh(t);
+    const int t = lane_t(wid);
 #pragma unroll
     for (int it = 0; it < 16; ++it) {
         const int f = it * 512 + t;
@@ -473,9 +517,9 @@ __device__ __forceinline__ void put_rowhalf(float* T, int t, const float (&q)[64
     }
 }
 template <int HF>
-__device__ __forceinline__ void out_rowhalf(gfloat* dst, const float* T, int t)
+__device__ __forceinline__ void out_rowhalf(gfloat* dst, const float* T, int wid)
 {
-    t = fresh(t);
+    const int t = lane_t(wid);
 #pragma unroll
     for (int it = 0; it < 16; ++it) {
         const int f = it * 512 + t;
@@ -486,40 +530,43 @@ __device__ __forceinline__ void out_rowhalf(gfloat* dst, const float* T, int t)
 
 // ---- forward rows through the column-half stage: row i; group 0: u[n] = x[n] +
 // x[255-n] -> DCT-II_128 (even outputs), group 1: w[n] = x[n] - x[255-n] -> DCT-IV_128
-// (odd outputs).  Four barriers: left half in, read, right half in, read.
+// (odd outputs); n < 64 from the outer half, 64 <= n < 128 from the inner half.  Four
+// barriers: outer half in, read, inner half in, read.
 template <int G>
-__device__ __forceinline__ void rows_fwd(const gfloat* src, float* T, int t, int i, float (&R)[H], twptr tw)
+__device__ __forceinline__ void rows_from_stage(const float* T, int wid, float (&v)[H], int base)
 {
-    float xl[H];
-    {
-        float qa[64], qb[64];
-        load_colhalf<0>(src, t, qa);
-        load_colhalf<1>(src, t, qb);
-        __syncthreads(); // earlier readers of the LDS are done
-        put_colhalf(T, t, qa);
-        __syncthreads();
-        int r = fresh(i);
+    int r = lane_t(wid) & 255;
 #pragma unroll
-        for (int j = 0; j < H / 4; ++j) {
-            const float4 a = *reinterpret_cast<const float4*>(&T[r * CP + 4 * j]);
-            xl[4 * j] = a.x; xl[4 * j + 1] = a.y; xl[4 * j + 2] = a.z; xl[4 * j + 3] = a.w;
-            if (j % 8 == 7) after(r, a.w);
+    for (int j = 0; j < 16; ++j) {
+        const float4 lo = *reinterpret_cast<const float4*>(&T[r * CP + 4 * j]);       // x[k .. k+3]
+        const float4 hi = *reinterpret_cast<const float4*>(&T[r * CP + H - 4 - 4 * j]); // x[252-k .. 255-k]
+        const float xl[4] = {lo.x, lo.y, lo.z, lo.w};
+        const float xh[4] = {hi.w, hi.z, hi.y, hi.x}; // x[255 - (k + q)]
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[base + 4 * j + q] = G == 0 ? xl[q] + xh[q] : xl[q] - xh[q];
+        if (j % 8 == 7) after(r, v[base + 4 * j + 3]);
+    }
+}
+template <int G>
+__device__ __forceinline__ void rows_fwd(const gfloat* src, float* T, int wid, float (&R)[H], twptr tw)
+{
+    float v[H];
+    {
+        float qb[64];
+        {
+            float qa[64];
+            load_colhalf<0>(src, wid, qa);
+            load_colhalf<1>(src, wid, qb);
+            __syncthreads(); // earlier readers of the LDS are done
+            put_colhalf(T, wid, qa);
         }
         __syncthreads();
-        put_colhalf(T, t, qb);
+        rows_from_stage<G>(T, wid, v, 0);
         __syncthreads();
+        put_colhalf(T, wid, qb);
     }
-    float v[H];
-    int r = fresh(i);
-#pragma unroll
-    for (int j = 0; j < H / 4; ++j) {
-        // stage column 124 - 4j .. 127 - 4j holds x[252 - 4j .. 255 - 4j]
-        const float4 b = *reinterpret_cast<const float4*>(&T[r * CP + H - 4 - 4 * j]);
-        const float xh[4] = {b.w, b.z, b.y, b.x}; // x[255 - (4j + q)]
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[4 * j + q] = G == 0 ? xl[4 * j + q] + xh[q] : xl[4 * j + q] - xh[q];
-        if (j % 8 == 7) after(r, v[4 * j + 3]);
-    }
+    __syncthreads();
+    rows_from_stage<G>(T, wid, v, H / 2);
     if constexpr (G == 0) dct2_rec<L, H>(v, R, tw); else dct4_scaled<L, H>(v, R, tw);
 }
 
@@ -527,27 +574,27 @@ __device__ __forceinline__ void rows_fwd(const gfloat* src, float* T, int t, int
 // coefficient rows -> DCT-III_128 (a), CR 1: odd coefficient rows -> DCT-IV_128 (b).
 // Four barriers, as rows_fwd.
 template <int G, int CR>
-__device__ __forceinline__ void cols_inv(const gfloat* src, float* T, int t, int cc, float (&R)[H], twptr tw)
+__device__ __forceinline__ void cols_inv(const gfloat* src, float* T, int wid, float (&R)[H], twptr tw)
 {
     float v[H];
     {
         float qa[64], qb[64];
-        load_rowhalf<0>(src, t, qa);
-        load_rowhalf<1>(src, t, qb);
+        load_rowhalf<0>(src, wid, qa);
+        load_rowhalf<1>(src, wid, qb);
         __syncthreads();
-        put_rowhalf(T, t, qa);
+        put_rowhalf(T, wid, qa);
         __syncthreads();
-        int c = fresh(cc);
+        int c = lane_t(wid) & 127;
 #pragma unroll
         for (int k = 0; k < H / 2; ++k) {
             v[k] = T[(2 * k + CR) * RP + 2 * c + G];
             if (k % 32 == 31) after(c, v[k]);
         }
         __syncthreads();
-        put_rowhalf(T, t, qb);
+        put_rowhalf(T, wid, qb);
         __syncthreads();
     }
-    int c = fresh(cc);
+    int c = lane_t(wid) & 127;
 #pragma unroll
     for (int k = H / 2; k < H; ++k) {
         v[k] = T[(2 * k + CR - H) * RP + 2 * c + G];
@@ -557,9 +604,9 @@ __device__ __forceinline__ void cols_inv(const gfloat* src, float* T, int t, int
 }
 
 // Row i of the tile <- the thread's 128 values.
-__device__ __forceinline__ void put_row(float* T, int i, const float (&R)[H])
+__device__ __forceinline__ void put_row(float* T, int wid, const float (&R)[H])
 {
-    i = fresh(i);
+    const int i = lane_t(wid) & 255;
 #pragma unroll
     for (int k = 0; k < H; ++k) T[i * P + k] = R[k];
 }
@@ -567,9 +614,9 @@ __device__ __forceinline__ void put_row(float* T, int i, const float (&R)[H])
 // Forward transform of tile column cc (256 values down the tile rows): CR 0 -> even
 // coefficients (DCT-II_128 of u), CR 1 -> odd coefficients (DCT-IV_128 of w).
 template <int CR>
-__device__ __forceinline__ void col_fwd(const float* T, int cc, float (&o)[H], twptr tw)
+__device__ __forceinline__ void col_fwd(const float* T, int wid, float (&o)[H], twptr tw)
 {
-    cc = fresh(cc);
+    int cc = lane_t(wid) & 127;
     float v[H];
 #pragma unroll
     for (int n = 0; n < H; ++n) {
@@ -590,9 +637,9 @@ __device__ __forceinline__ void col_inv(const float (&o)[H], float (&R)[H], twpt
 
 // Column halves into the tile: rows 0..127 hold a, rows 128..255 hold b (column cc).
 template <int CR>
-__device__ __forceinline__ void put_halves(float* T, int cc, const float (&R)[H])
+__device__ __forceinline__ void put_halves(float* T, int wid, const float (&R)[H])
 {
-    cc = fresh(cc);
+    const int cc = lane_t(wid) & 127;
 #pragma unroll
     for (int n = 0; n < H; ++n) T[(CR * H + n) * P + cc] = R[n];
 }
@@ -601,9 +648,9 @@ __device__ __forceinline__ void put_halves(float* T, int cc, const float (&R)[H]
 // Z[i][.] = a[r] + b[r] (i < 128, r = i) or a[r] - b[r] (r = 255 - i).  Group 0 has
 // the even entries (DCT-III_128), group 1 the odd entries (DCT-IV_128).
 template <int G>
-__device__ __forceinline__ void row_inv(const float* T, int i, float (&R)[H], twptr tw)
+__device__ __forceinline__ void row_inv(const float* T, int wid, float (&R)[H], twptr tw)
 {
-    i = fresh(i);
+    const int i = lane_t(wid) & 255;
     const bool top = i < H;
     int r = top ? i : L - 1 - i;
     const float sg = top ? 1.f : -1.f; // exact: one rounding, as a +- b
@@ -619,164 +666,171 @@ __device__ __forceinline__ void row_inv(const float* T, int i, float (&R)[H], tw
 // ---- forward output: coefficient rows 2k + CR (k in half HF of 0..127) of column
 // 2 cc + G into the row-half stage, then out.  Four barriers with the stage windows.
 template <int G, int CR>
-__device__ __forceinline__ void coefs_out(gfloat* dst, float* T, int t, int cc, const float (&o)[H])
+__device__ __forceinline__ void coefs_out(gfloat* dst, float* T, int wid, const float (&o)[H])
 {
     {
-        const int c = fresh(cc);
+        const int c = lane_t(wid) & 127;
 #pragma unroll
         for (int k = 0; k < H / 2; ++k) T[(2 * k + CR) * RP + 2 * c + G] = o[k];
     }
     __syncthreads();
-    out_rowhalf<0>(dst, T, t);
+    out_rowhalf<0>(dst, T, wid);
     __syncthreads();
     {
-        const int c = fresh(cc);
+        const int c = lane_t(wid) & 127;
 #pragma unroll
         for (int k = H / 2; k < H; ++k) T[(2 * k + CR - H) * RP + 2 * c + G] = o[k];
     }
     __syncthreads();
-    out_rowhalf<1>(dst, T, t);
+    out_rowhalf<1>(dst, T, wid);
 }
 
-// ---- inverse output by column halves: x[i][m] = p[m] + q[m] (left), x[i][255-m] =
-// p[m] - q[m] (right, stage column 127 - m); group 0 writes p, then group 1 adds or
-// subtracts q.  Five barriers.
+// ---- inverse output by column halves: x[i][m] = p[m] + q[m], x[i][255-m] = p[m] -
+// q[m], m < 64 through the outer half, 64 <= m < 128 through the inner half (stage
+// columns m mod 64 and 127 - m mod 64); group 0 writes p into both places, then group 1
+// adds and subtracts q.  Five barriers.
 template <int G>
-__device__ __forceinline__ void rows_out(gfloat* dst, float* T, int t, int i, const float (&R)[H])
+__device__ __forceinline__ void rows_out(gfloat* dst, float* T, int wid, const float (&R)[H])
 {
 #pragma unroll
     for (int hf = 0; hf < 2; ++hf) {
-        const int r = fresh(i);
+        const int r = lane_t(wid) & 255;
+        const int m0 = hf * (H / 2);
         if (G == 0) {
 #pragma unroll
-            for (int j = 0; j < H / 4; ++j) {
-                float4* d = reinterpret_cast<float4*>(&T[r * CP + (hf == 0 ? 4 * j : H - 4 - 4 * j)]);
-                *d = hf == 0 ? make_float4(R[4 * j], R[4 * j + 1], R[4 * j + 2], R[4 * j + 3])
-                             : make_float4(R[4 * j + 3], R[4 * j + 2], R[4 * j + 1], R[4 * j]);
+            for (int j = 0; j < 16; ++j) {
+                const float* p = &R[m0 + 4 * j];
+                *reinterpret_cast<float4*>(&T[r * CP + 4 * j]) = make_float4(p[0], p[1], p[2], p[3]);
+                *reinterpret_cast<float4*>(&T[r * CP + H - 4 - 4 * j]) = make_float4(p[3], p[2], p[1], p[0]);
             }
         }
         __syncthreads();
         if (G == 1) {
 #pragma unroll
-            for (int j = 0; j < H / 4; ++j) {
-                float4* d = reinterpret_cast<float4*>(&T[r * CP + (hf == 0 ? 4 * j : H - 4 - 4 * j)]);
-                float4 s = *d;
-                if (hf == 0) {
-                    s.x += R[4 * j]; s.y += R[4 * j + 1]; s.z += R[4 * j + 2]; s.w += R[4 * j + 3];
-                } else {
-                    s.w -= R[4 * j]; s.z -= R[4 * j + 1]; s.y -= R[4 * j + 2]; s.x -= R[4 * j + 3];
-                }
-                *d = s;
+            for (int j = 0; j < 16; ++j) {
+                const float* q = &R[m0 + 4 * j];
+                float4* lo = reinterpret_cast<float4*>(&T[r * CP + 4 * j]);
+                float4* hi = reinterpret_cast<float4*>(&T[r * CP + H - 4 - 4 * j]);
+                float4 a = *lo, b = *hi;
+                a.x += q[0]; a.y += q[1]; a.z += q[2]; a.w += q[3];
+                b.w -= q[0]; b.z -= q[1]; b.y -= q[2]; b.x -= q[3];
+                *lo = a;
+                *hi = b;
             }
         }
         __syncthreads();
-        if (hf == 0) out_colhalf<0>(dst, T, t); else out_colhalf<1>(dst, T, t);
+        if (hf == 0) out_colhalf<0>(dst, T, wid); else out_colhalf<1>(dst, T, wid);
         if (hf == 0) __syncthreads();
     }
 }
 
 // One (group, column half) path of one array.
 template <int DIR, int G, int CR>
-__device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, int t, int i, int cc, twptr tw)
+__device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, int wid, twptr tw)
 {
     float R[H];
     if constexpr (DIR == DCT2D_FORWARD) {
-        rows_fwd<G>(src, T, t, i, R, tw);
+        rows_fwd<G>(src, T, wid, R, tw);
         float o[H];
         tw_fence(tw);
         if constexpr (G == 0) {
             __syncthreads(); // stage reads done
-            put_row(T, i, R);
+            put_row(T, wid, R);
             __syncthreads();
-            col_fwd<CR>(T, cc, o, tw);
+            col_fwd<CR>(T, wid, o, tw);
             syncs(3); // round O
         } else {
             syncs(3); // round E
-            put_row(T, i, R);
+            put_row(T, wid, R);
             __syncthreads();
-            col_fwd<CR>(T, cc, o, tw);
+            col_fwd<CR>(T, wid, o, tw);
             __syncthreads();
         }
-        coefs_out<G, CR>(dst, T, t, cc, o);
+        coefs_out<G, CR>(dst, T, wid, o);
     } else {
         if constexpr (DIR == DCT2D_INVERSE) {
-            cols_inv<G, CR>(src, T, t, cc, R, tw);
+            cols_inv<G, CR>(src, T, wid, R, tw);
             tw_fence(tw);
             if constexpr (G == 0) {
                 __syncthreads();
-                put_halves<CR>(T, cc, R);
+                put_halves<CR>(T, wid, R);
                 __syncthreads();
-                row_inv<0>(T, i, R, tw); // p
+                row_inv<0>(T, wid, R, tw); // p
                 syncs(3);                // round O
             } else {
                 syncs(3); // round E
-                put_halves<CR>(T, cc, R);
+                put_halves<CR>(T, wid, R);
                 __syncthreads();
-                row_inv<1>(T, i, R, tw); // q
+                row_inv<1>(T, wid, R, tw); // q
                 __syncthreads();
             }
         } else {
-            rows_fwd<G>(src, T, t, i, R, tw);
+            rows_fwd<G>(src, T, wid, R, tw);
             tw_fence(tw);
             if constexpr (G == 0) {
                 __syncthreads();
-                put_row(T, i, R);
+                put_row(T, wid, R);
                 __syncthreads();
                 {
                     float o[H];
-                    col_fwd<CR>(T, cc, o, tw);
+                    col_fwd<CR>(T, wid, o, tw);
                     tw_fence(tw);
                     col_inv<CR>(o, R, tw);
                 }
                 __syncthreads();
-                put_halves<CR>(T, cc, R);
+                put_halves<CR>(T, wid, R);
                 __syncthreads();
-                row_inv<0>(T, i, R, tw); // p
+                row_inv<0>(T, wid, R, tw); // p
                 syncs(5);                // round O
             } else {
                 syncs(5); // round E
-                put_row(T, i, R);
+                put_row(T, wid, R);
                 __syncthreads();
                 {
                     float o[H];
-                    col_fwd<CR>(T, cc, o, tw);
+                    col_fwd<CR>(T, wid, o, tw);
                     tw_fence(tw);
                     col_inv<CR>(o, R, tw);
                 }
                 __syncthreads();
-                put_halves<CR>(T, cc, R);
+                put_halves<CR>(T, wid, R);
                 __syncthreads();
-                row_inv<1>(T, i, R, tw); // q
+                row_inv<1>(T, wid, R, tw); // q
                 __syncthreads();
             }
         }
-        rows_out<G>(dst, T, t, i, R);
+        rows_out<G>(dst, T, wid, R);
     }
 }
 } // namespace s256
 
+// `stagger`: workgroups of the second cohort (every other one on each XCD) first idle for
+// about stagger x 8k cycles, so that the two cohorts' HBM phases (the array in, the
+// array out) fall into each other's compute phases instead of coinciding on every CU.
 template <int DIR>
 __global__ void __launch_bounds__(512, 1)
-k_split256(Addr a, int64_t batch, const float2* __restrict__ tw_in)
+k_split256(Addr a, int64_t batch, const float2* __restrict__ tw_in, int stagger)
 {
     using namespace s256;
     __shared__ float4 T4[LDS_FLOATS / 4];
     float* const T = reinterpret_cast<float*>(T4);
-    const int t = threadIdx.x;
-    const int g = __builtin_amdgcn_readfirstlane(t >> 8);        // group, uniform per wavefront
-    const int cr = __builtin_amdgcn_readfirstlane((t >> 7) & 1); // column half, uniform per wavefront
-    const int i = t & 255;  // row of the row phases
-    const int cc = t & 127; // column slot of the column phases: column 2 cc + group
+    if ((blockIdx.x >> 3) & 1)
+        for (int k = 0; k < stagger; ++k) __builtin_amdgcn_s_sleep(127);
+    // wavefront index w: group w / 4 (E, O), column half (w / 2) % 2; thread t = 64 w + lane,
+    // row of the row phases t % 256, column slot of the column phases t % 128 (column
+    // 2 (t % 128) + group)
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = wid >> 2, cr = (wid >> 1) & 1;
     for (int64_t blk = blockIdx.x; blk < batch; blk += gridDim.x) {
         const twptr tw = per_iteration(tw_in);
         const gfloat* src = uniform_ptr(a.src(blk));
         gfloat* dst = uniform_ptr(a.dst(blk));
         if (g == 0) {
-            if (cr == 0) path<DIR, 0, 0>(src, dst, T, t, i, cc, tw);
-            else path<DIR, 0, 1>(src, dst, T, t, i, cc, tw);
+            if (cr == 0) path<DIR, 0, 0>(src, dst, T, wid, tw);
+            else path<DIR, 0, 1>(src, dst, T, wid, tw);
         } else {
-            if (cr == 0) path<DIR, 1, 0>(src, dst, T, t, i, cc, tw);
-            else path<DIR, 1, 1>(src, dst, T, t, i, cc, tw);
+            if (cr == 0) path<DIR, 1, 0>(src, dst, T, wid, tw);
+            else path<DIR, 1, 1>(src, dst, T, wid, tw);
         }
     }
 }
@@ -916,24 +970,28 @@ int launch_wave(const DeviceTables* t, const Job& j)
     }
 }
 
-template <int DIR>
+template <int DIR, bool STAGE>
 int launch_split128_dir(const DeviceTables* t, const Job& j)
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_split128<DIR>, 256, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_split128<DIR, STAGE>, 256, 0) != hipSuccess ||
+        per_cu < 1)
         per_cu = 1;
     const int64_t cap = (int64_t)t->num_cu * per_cu * 4;
     const unsigned grid = (unsigned)(j.batch < cap ? j.batch : cap);
-    k_split128<DIR><<<grid, 256, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, 128));
+    k_split128<DIR, STAGE><<<grid, 256, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, 128));
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
 }
 
-int launch_split128(const DeviceTables* t, const Job& j)
+int launch_split128(const DeviceTables* t, const Job& j, bool stage)
 {
     switch (j.dir) {
-    case DCT2D_FORWARD: return launch_split128_dir<DCT2D_FORWARD>(t, j);
-    case DCT2D_INVERSE: return launch_split128_dir<DCT2D_INVERSE>(t, j);
-    default: return launch_split128_dir<DCT2D_ROUNDTRIP>(t, j);
+    case DCT2D_FORWARD:
+        return stage ? launch_split128_dir<DCT2D_FORWARD, true>(t, j) : launch_split128_dir<DCT2D_FORWARD, false>(t, j);
+    case DCT2D_INVERSE: return launch_split128_dir<DCT2D_INVERSE, false>(t, j); // reads coalesced already
+    default:
+        return stage ? launch_split128_dir<DCT2D_ROUNDTRIP, true>(t, j)
+                     : launch_split128_dir<DCT2D_ROUNDTRIP, false>(t, j);
     }
 }
 
@@ -943,10 +1001,12 @@ int launch_split256_dir(const DeviceTables* t, const Job& j)
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_split256<DIR>, 512, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
-    // variant 0: one resident workgroup per CU looping over arrays; variant 2: one array per workgroup
+    // variant 0: one resident workgroup per CU looping over arrays; 2: one array per
+    // workgroup; 3, 4: as 0 with the second cohort started about 3 x 8k / 6 x 8k cycles late
     const int64_t cap = j.variant == 2 ? ((int64_t)1 << 31) - 1 : (int64_t)t->num_cu * per_cu;
     const unsigned grid = (unsigned)(j.batch < cap ? j.batch : cap);
-    k_split256<DIR><<<grid, 512, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, 256));
+    const int stagger = j.variant == 3 ? 3 : j.variant == 4 ? 6 : 0;
+    k_split256<DIR><<<grid, 512, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, 256), stagger);
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
 }
 
@@ -1060,19 +1120,30 @@ int launch_fused(const DeviceTables* t, const Job& j)
 // Variants (frozen per size by the policy table / autotuner):
 //   both axes <= 64:  0 wave-local fused, 1 LDS-staged fused, 2 two-pass,
 //                     3 wave-local fused with one tile per workgroup
-//   128 x 128:        0 split fused (two wavefronts per transform), 1 LDS-staged fused, 2 two-pass
+//   128 x 128:        0 split fused (two wavefronts per transform), 1 LDS-staged fused, 2 two-pass,
+//                     3 split fused with the rows read through an LDS copy of the array
 //   other axes <=128: 0 LDS-staged fused, 1 two-pass
 //   256 x 256:        0 split fused (two groups of wavefronts, two LDS rounds), one
 //                     resident workgroup per CU; 1 two-pass; 2 split fused, one array
-//                     per workgroup
+//                     per workgroup; 3, 4 as 0 with the two cohorts of CUs staggered
 //   other, an axis of 256: 0 two-pass
 int fp32_variant_count(int rows, int cols, int)
 {
     if (rows <= 64 && cols <= 64) return 4;
-    if (rows == 128 && cols == 128) return 3;
+    if (rows == 128 && cols == 128) return 4;
     if (rows <= 128 && cols <= 128) return 2;
-    if (rows == 256 && cols == 256) return 3;
+    if (rows == 256 && cols == 256) return 5;
     return 1;
+}
+
+// Variant used until the tuner measures otherwise (fastest in measurements on MI355X
+// with 512 MiB batches): wave-local with one tile per workgroup for axes <= 64, the
+// staged split kernel for 128 x 128, the split kernel for 256 x 256.
+int fp32_default_variant(int rows, int cols, int dir)
+{
+    if (rows <= 64 && cols <= 64) return 3;
+    if (rows == 128 && cols == 128) return dir == DCT2D_INVERSE ? 0 : 3;
+    return 0;
 }
 
 int launch_fp32(const DeviceTables* t, const Job& j)
@@ -1083,7 +1154,7 @@ int launch_fp32(const DeviceTables* t, const Job& j)
         return launch_two_pass(t, j);
     }
     if (j.rows == 128 && j.cols == 128) {
-        if (j.variant == 0) return launch_split128(t, j);
+        if (j.variant == 0 || j.variant == 3) return launch_split128(t, j, j.variant == 3);
         if (j.variant == 1) return launch_fused(t, j);
         return launch_two_pass(t, j);
     }
