@@ -152,16 +152,19 @@ def main():
             per[str(n)][d] = {"ms": round(ms, 4), "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                               "transforms_per_s": round(host[n].shape[0] / (ms * 1e-3), 1)}
 
-    # dominant kernel: the call with the largest share of the step among single-kernel calls
-    single = [(n, d) for n in sizes for d in DIRS if n <= 128]
+    # dominant kernel: the call with the largest share of the step among calls that are one
+    # kernel launch (the event pair then brackets exactly that kernel)
+    names = {(n, d): kernel_name(n, d, tuned["%d/%s" % (n, d)]) for n in sizes for d in DIRS}
+    single = [k for k in names if names[k]]
     dom = max(single, key=lambda k: call_ms[k]) if single else max(call_ms, key=call_ms.get)
     n_dom, d_dom = dom
     alg_bytes = 8 * n_dom * n_dom * host[n_dom].shape[0]
     achieved = alg_bytes / (call_ms[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "fused fp32 %s N=%d" % (d_dom, n_dom), "avg_ms": round(call_ms[dom], 4),
-                "algorithmic_bytes_per_launch": alg_bytes}
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": counted_traffic(names[dom]) if names.get(dom) else None,
+                "kernel": names.get(dom) or "%s N=%d" % (d_dom, n_dom), "call": "%s N=%d" % (d_dom, n_dom),
+                "avg_ms": round(call_ms[dom], 4), "algorithmic_bytes_per_launch": alg_bytes}
 
     # ---- float32 vs split-precision matrix paths (same GPU, same inputs) --------------
     compare = {}
@@ -204,6 +207,54 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(host, sizes, args.cpu_frac, bufs, stream)
     print(json.dumps(out), flush=True)
+
+
+def kernel_name(n, d, tuned):
+    """Kernel that one call launches (as rocprofv3 names it), or None for multi-kernel schedules.
+    `tuned` is "path/vK" as frozen by the policy."""
+    path, v = tuned.split("/v")
+    v = int(v)
+    di = DIRS.index(d)
+    if path != "fp32":
+        return None
+    if n <= 64:
+        return {0: "k_wave<%d, %d, %d>", 3: "k_wave<%d, %d, %d>", 1: "k_fused<%d, %d, %d>"}.get(v, "") % (n, n, di) \
+            if v in (0, 1, 3) else None
+    if n == 128:
+        if v in (0, 3):
+            return "k_split128<%d, %s>" % (di, "true" if v == 3 and d != "inverse" else "false")
+        return "k_fused<128, 128, %d>" % di if v == 1 else None
+    if n == 256:
+        return None if v == 1 else "k_split256<%d>" % di
+    return None
+
+
+def source_digest():
+    """SHA-256 over the kernel sources; ties counter-derived traffic figures to the code they measured."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2609_28519_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def counted_traffic(kernel):
+    """Calibrated HBM bytes per dispatch of `kernel` (FETCH_SIZE x fetch factor + WRITE_SIZE x write
+    factor, from two rocprofv3 counter passes, recorded in profiles/hbm_traffic.json), or None when
+    the counters were taken on other kernel sources or do not cover this kernel."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_digest() or kernel not in rec.get("kernels", {}):
+        return None
+    k = rec["kernels"][kernel]
+    return int(k["read_bytes"] + k["write_bytes"])
 
 
 def ragged_c4(dct, stream, steps):
