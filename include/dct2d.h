@@ -19,10 +19,11 @@
  *
  * Pointers: `data`, `in`, `out` and ragged `base` are DEVICE pointers (memory the
  * caller allocated on the current HIP device, e.g. through PyTorch).  The caller
- * owns them; the library never frees or retains them past the call, except that a
- * ragged plan remembers nothing about them either -- the base pointer is passed to
- * every execute call.  Host pointers are accepted only where stated (descriptor
- * arrays of the ragged planner).
+ * owns them; the library never frees them and keeps none of them past the call.  A
+ * ragged plan receives its base pointer on every execute call and keeps only a device
+ * copy of the last one (to skip the 8-byte update when it repeats); it never
+ * dereferences it outside an execute.  Host pointers are accepted only where stated
+ * (descriptor arrays of the ragged planner).
  *
  * Streams: `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  * transform calls only enqueue work and return; results are visible after the
@@ -75,7 +76,7 @@ extern "C" {
  * DCT2D_FP32        float32 fast transforms on the vector ALU (all sizes).
  * DCT2D_SPLIT_BF16X3  dense Q X Q^T on MFMA, bf16 two-way split of Q and X, three
  *                   products (hi*hi + hi*lo + lo*hi), fp32 accumulation, per-block
- *                   power-of-two scaling.  rows = cols <= 32.  Not float32-accurate
+ *                   power-of-two scaling.  rows = cols <= 64.  Not float32-accurate
  *                   (~16 significant bits); reported, not gated.
  * DCT2D_SPLIT_BF16X6  as above with a three-way bf16 split and the six products
  *                   whose split indices sum to <= 2; float32-accurate.
