@@ -436,6 +436,18 @@ __device__ __forceinline__ void after(int& idx, float dep)
     asm volatile("" : "+v"(idx) : "v"(dep));
 }
 
+// Pins a transform's results before the next workgroup barrier.  The compiler may
+// otherwise move pure arithmetic across a barrier (it only orders memory operations),
+// which pushes the tail of a group's transform into the phase after the barrier and
+// defeats the overlap of the two groups' work.  Empty asm statements that "modify"
+// every value are ordered with the barrier and so must follow the arithmetic.
+template <int N>
+__device__ __forceinline__ void settle(float (&v)[N])
+{
+#pragma unroll
+    for (int k = 0; k < N; ++k) asm volatile("" : "+v"(v[k]));
+}
+
 __device__ __forceinline__ void syncs(int n)
 {
     for (int k = 0; k < n; ++k) __syncthreads();
@@ -568,6 +580,7 @@ __device__ __forceinline__ void rows_fwd(const gfloat* src, float* T, int wid, f
     __syncthreads();
     rows_from_stage<G>(T, wid, v, H / 2);
     if constexpr (G == 0) dct2_rec<L, H>(v, R, tw); else dct4_scaled<L, H>(v, R, tw);
+    settle(R);
 }
 
 // ---- inverse columns through the row-half stage: column 2 cc + G; CR 0: even
@@ -601,6 +614,7 @@ __device__ __forceinline__ void cols_inv(const gfloat* src, float* T, int wid, f
         if (k % 32 == 31) after(c, v[k]);
     }
     if constexpr (CR == 0) dct3_rec<L, H>(v, R, tw); else dct4_scaled<L, H>(v, R, tw);
+    settle(R);
 }
 
 // Row i of the tile <- the thread's 128 values.
@@ -625,6 +639,7 @@ __device__ __forceinline__ void col_fwd(const float* T, int wid, float (&o)[H], 
         if (n % 32 == 31) after(cc, v[n]);
     }
     if constexpr (CR == 0) dct2_rec<L, H>(v, o, tw); else dct4_scaled<L, H>(v, o, tw);
+    settle(o);
 }
 
 // Inverse of the same column half: CR 0: DCT-III_128 of the even coefficients (a),
@@ -633,6 +648,7 @@ template <int CR>
 __device__ __forceinline__ void col_inv(const float (&o)[H], float (&R)[H], twptr tw)
 {
     if constexpr (CR == 0) dct3_rec<L, H>(o, R, tw); else dct4_scaled<L, H>(o, R, tw);
+    settle(R);
 }
 
 // Column halves into the tile: rows 0..127 hold a, rows 128..255 hold b (column cc).
@@ -661,6 +677,7 @@ __device__ __forceinline__ void row_inv(const float* T, int wid, float (&R)[H], 
         if (c % 32 == 31) after(r, o[c]);
     }
     if constexpr (G == 0) dct3_rec<L, H>(o, R, tw); else dct4_scaled<L, H>(o, R, tw);
+    settle(R);
 }
 
 // ---- forward output: coefficient rows 2k + CR (k in half HF of 0..127) of column
