@@ -222,7 +222,7 @@ def kernel_name(n, d, tuned):
             if v in (0, 1, 3) else None
     if n == 128:
         if v in (0, 3):
-            return "k_split128<%d, %s>" % (di, "true" if v == 3 and d != "inverse" else "false")
+            return "k_split128<%d, %s>" % (di, "true" if v == 3 else "false")
         return "k_fused<128, 128, %d>" % di if v == 1 else None
     if n == 256:
         return None if v == 1 else "k_split256<%d>" % di

@@ -256,9 +256,9 @@ k_wave(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* _
 //   round trip: forward rows | forward + inverse columns in registers | inverse rows
 constexpr int S128_P = 129;
 
-// STAGE: the forward rows come from an LDS copy of the array (row pitch 132) filled with
-// coalesced 16-byte loads (each wavefront instruction covers two whole rows) instead of
-// each thread reading its own row from HBM.
+// STAGE: the forward rows (inverse columns) come from an LDS copy of the array (row pitch
+// 132) filled with coalesced 16-byte loads (each wavefront instruction covers two whole
+// rows) instead of each thread reading its own row (column) from HBM.
 template <int DIR, bool STAGE>
 __global__ void __launch_bounds__(256, 2) // two workgroups per CU: the LDS tile allows exactly two
 k_split128(Addr a, int64_t batch, const float2* __restrict__ tw_in)
@@ -338,9 +338,30 @@ k_split128(Addr a, int64_t batch, const float2* __restrict__ tw_in)
 #pragma unroll
             for (int n = 0; n < H; ++n) T[(role * H + n) * P + idx] = v[n];
         } else {
-            // ---- inverse columns: even (role 0) or odd (role 1) coefficient rows from HBM
+            // ---- inverse columns: even (role 0) or odd (role 1) coefficient rows
+            if (STAGE) {
+                // coalesced 16-byte loads into an LDS copy (pitch 132), then column idx from it
+                const DCT_GLOBAL char* sb = reinterpret_cast<const DCT_GLOBAL char*>(uniform_ptr(src));
+                float q[64];
 #pragma unroll
-            for (int k = 0; k < H; ++k) o[k] = src[(int64_t)(2 * k + role) * L + idx];
+                for (int it = 0; it < 16; ++it) {
+                    const float4 w = *reinterpret_cast<const gfloat4*>(sb + (uint32_t)((it * 256 + t) * 16));
+                    q[4 * it] = w.x; q[4 * it + 1] = w.y; q[4 * it + 2] = w.z; q[4 * it + 3] = w.w;
+                }
+#pragma unroll
+                for (int it = 0; it < 16; ++it) {
+                    const int f = it * 256 + t;
+                    *reinterpret_cast<float4*>(&T[(f >> 5) * SP + 4 * (f & 31)]) =
+                        make_float4(q[4 * it], q[4 * it + 1], q[4 * it + 2], q[4 * it + 3]);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < H; ++k) o[k] = T[(2 * k + role) * SP + idx];
+                __syncthreads(); // the staged copy is read before the halves overwrite it
+            } else {
+#pragma unroll
+                for (int k = 0; k < H; ++k) o[k] = src[(int64_t)(2 * k + role) * L + idx];
+            }
             if (role == 0) dct3_rec<L, H>(o, v, tw); else dct4_scaled<L, H>(o, v, tw);
 #pragma unroll
             for (int n = 0; n < H; ++n) T[(role * H + n) * P + idx] = v[n];
@@ -741,9 +762,30 @@ __device__ __forceinline__ void rows_out(gfloat* dst, float* T, int wid, const f
     }
 }
 
+// The idle stretch of a group (the other group's round): `n` barriers.  With `next` set
+// (the array this workgroup transforms after the current one), the group first issues
+// the loads of that array's first stage half and only consumes them (an empty asm use)
+// after the first barrier, so the reads travel while the other group computes: HBM is
+// otherwise idle during the rounds, and the later real loads of that half then come
+// from the device's caches.
+template <int DIR>
+__device__ __forceinline__ void idle(int n, const gfloat* next, int wid)
+{
+    if (next) {
+        float q[64];
+        if constexpr (DIR == DCT2D_INVERSE) load_rowhalf<0>(next, wid, q); else load_colhalf<0>(next, wid, q);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 64; ++k) asm volatile("" ::"v"(q[k]));
+        syncs(n - 1);
+    } else {
+        syncs(n);
+    }
+}
+
 // One (group, column half) path of one array.
 template <int DIR, int G, int CR>
-__device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, int wid, twptr tw)
+__device__ __forceinline__ void path(const gfloat* src, gfloat* dst, const gfloat* next, float* T, int wid, twptr tw)
 {
     float R[H];
     if constexpr (DIR == DCT2D_FORWARD) {
@@ -755,9 +797,9 @@ __device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, i
             put_row(T, wid, R);
             __syncthreads();
             col_fwd<CR>(T, wid, o, tw);
-            syncs(3); // round O
+            idle<DIR>(3, next, wid); // round O
         } else {
-            syncs(3); // round E
+            idle<DIR>(3, next, wid); // round E
             put_row(T, wid, R);
             __syncthreads();
             col_fwd<CR>(T, wid, o, tw);
@@ -773,9 +815,9 @@ __device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, i
                 put_halves<CR>(T, wid, R);
                 __syncthreads();
                 row_inv<0>(T, wid, R, tw); // p
-                syncs(3);                // round O
+                idle<DIR>(3, next, wid);   // round O
             } else {
-                syncs(3); // round E
+                idle<DIR>(3, next, wid); // round E
                 put_halves<CR>(T, wid, R);
                 __syncthreads();
                 row_inv<1>(T, wid, R, tw); // q
@@ -798,9 +840,9 @@ __device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, i
                 put_halves<CR>(T, wid, R);
                 __syncthreads();
                 row_inv<0>(T, wid, R, tw); // p
-                syncs(5);                // round O
+                idle<DIR>(5, next, wid);   // round O
             } else {
-                syncs(5); // round E
+                idle<DIR>(5, next, wid); // round E
                 put_row(T, wid, R);
                 __syncthreads();
                 {
@@ -826,7 +868,7 @@ __device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, i
 // array out) fall into each other's compute phases instead of coinciding on every CU.
 template <int DIR>
 __global__ void __launch_bounds__(512, 1)
-k_split256(Addr a, int64_t batch, const float2* __restrict__ tw_in, int stagger)
+k_split256(Addr a, int64_t batch, const float2* __restrict__ tw_in, int stagger, int prefetch)
 {
     using namespace s256;
     __shared__ float4 T4[LDS_FLOATS / 4];
@@ -842,12 +884,13 @@ k_split256(Addr a, int64_t batch, const float2* __restrict__ tw_in, int stagger)
         const twptr tw = per_iteration(tw_in);
         const gfloat* src = uniform_ptr(a.src(blk));
         gfloat* dst = uniform_ptr(a.dst(blk));
+        const gfloat* next = prefetch && blk + gridDim.x < batch ? uniform_ptr(a.src(blk + gridDim.x)) : nullptr;
         if (g == 0) {
-            if (cr == 0) path<DIR, 0, 0>(src, dst, T, wid, tw);
-            else path<DIR, 0, 1>(src, dst, T, wid, tw);
+            if (cr == 0) path<DIR, 0, 0>(src, dst, next, T, wid, tw);
+            else path<DIR, 0, 1>(src, dst, next, T, wid, tw);
         } else {
-            if (cr == 0) path<DIR, 1, 0>(src, dst, T, wid, tw);
-            else path<DIR, 1, 1>(src, dst, T, wid, tw);
+            if (cr == 0) path<DIR, 1, 0>(src, dst, next, T, wid, tw);
+            else path<DIR, 1, 1>(src, dst, next, T, wid, tw);
         }
     }
 }
@@ -1005,7 +1048,8 @@ int launch_split128(const DeviceTables* t, const Job& j, bool stage)
     switch (j.dir) {
     case DCT2D_FORWARD:
         return stage ? launch_split128_dir<DCT2D_FORWARD, true>(t, j) : launch_split128_dir<DCT2D_FORWARD, false>(t, j);
-    case DCT2D_INVERSE: return launch_split128_dir<DCT2D_INVERSE, false>(t, j); // reads coalesced already
+    case DCT2D_INVERSE:
+        return stage ? launch_split128_dir<DCT2D_INVERSE, true>(t, j) : launch_split128_dir<DCT2D_INVERSE, false>(t, j);
     default:
         return stage ? launch_split128_dir<DCT2D_ROUNDTRIP, true>(t, j)
                      : launch_split128_dir<DCT2D_ROUNDTRIP, false>(t, j);
@@ -1019,11 +1063,13 @@ int launch_split256_dir(const DeviceTables* t, const Job& j)
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_split256<DIR>, 512, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
     // variant 0: one resident workgroup per CU looping over arrays; 2: one array per
-    // workgroup; 3, 4: as 0 with the second cohort started about 3 x 8k / 6 x 8k cycles late
+    // workgroup; 3, 4: as 0 with the second cohort started about 3 x 8k / 6 x 8k cycles late;
+    // 5: as 0 with the next array's first half read during the idle rounds
     const int64_t cap = j.variant == 2 ? ((int64_t)1 << 31) - 1 : (int64_t)t->num_cu * per_cu;
     const unsigned grid = (unsigned)(j.batch < cap ? j.batch : cap);
     const int stagger = j.variant == 3 ? 3 : j.variant == 4 ? 6 : 0;
-    k_split256<DIR><<<grid, 512, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, 256), stagger);
+    const int prefetch = j.variant >= 5 ? 1 : 0;
+    k_split256<DIR><<<grid, 512, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, 256), stagger, prefetch);
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
 }
 
@@ -1138,18 +1184,20 @@ int launch_fused(const DeviceTables* t, const Job& j)
 //   both axes <= 64:  0 wave-local fused, 1 LDS-staged fused, 2 two-pass,
 //                     3 wave-local fused with one tile per workgroup
 //   128 x 128:        0 split fused (two wavefronts per transform), 1 LDS-staged fused, 2 two-pass,
-//                     3 split fused with the rows read through an LDS copy of the array
+//                     3 split fused with the rows (inverse: columns) read through an LDS copy
+//                     of the array
 //   other axes <=128: 0 LDS-staged fused, 1 two-pass
 //   256 x 256:        0 split fused (two groups of wavefronts, two LDS rounds), one
 //                     resident workgroup per CU; 1 two-pass; 2 split fused, one array
-//                     per workgroup; 3, 4 as 0 with the two cohorts of CUs staggered
+//                     per workgroup; 3, 4 as 0 with the two cohorts of CUs staggered; 5 as
+//                     0 with the next array's first half prefetched during idle rounds
 //   other, an axis of 256: 0 two-pass
 int fp32_variant_count(int rows, int cols, int)
 {
     if (rows <= 64 && cols <= 64) return 4;
     if (rows == 128 && cols == 128) return 4;
     if (rows <= 128 && cols <= 128) return 2;
-    if (rows == 256 && cols == 256) return 5;
+    if (rows == 256 && cols == 256) return 6;
     return 1;
 }
 
