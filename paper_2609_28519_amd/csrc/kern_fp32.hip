@@ -384,19 +384,21 @@ k_split128(Addr a, int64_t batch, const float2* __restrict__ tw_in)
 #pragma unroll
         for (int n = 0; n < H; ++n) T[idx * P + role * H + n] = v[n];
         __syncthreads();
-        // ---- store: x[r][n] = a[n] + b[n], x[r][127-n] = a[n] - b[n]; 4 columns per thread
+        // ---- store: x[r][n] = a[n] + b[n], x[r][127-n] = a[n] - b[n].  Lane t covers column
+        // t % 128 of rows 2i + t / 128: consecutive lanes read consecutive LDS words (no bank
+        // conflicts) and write 256-byte segments.
+        {
+            int c = t & (L - 1);
+            asm volatile("" : "+v"(c)); // per array: keeps the 128 offsets below out of the loop preheader
+            const int cs = c < H ? c : L - 1 - c;
+            const float sg = c < H ? 1.f : -1.f; // exact: one rounding, as a +- b
+            DCT_GLOBAL char* db = reinterpret_cast<DCT_GLOBAL char*>(uniform_ptr(dst));
 #pragma unroll
-        for (int i = 0; i < L * L / (4 * 256); ++i) {
-            const int e = (i * 256 + t) * 4;
-            const int r = e / L, c0 = e % L;
-            float q[4];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int c = c0 + m;
-                q[m] = c < H ? T[r * P + c] + T[r * P + H + c]
-                             : T[r * P + (L - 1 - c)] - T[r * P + H + (L - 1 - c)];
+            for (int i = 0; i < L / 2; ++i) {
+                const int r = 2 * i + (t >> 7);
+                *reinterpret_cast<gfloat*>(db + (uint32_t)((r * L + c) * 4)) =
+                    __builtin_fmaf(sg, T[r * P + H + cs], T[r * P + cs]);
             }
-            *reinterpret_cast<gfloat4*>(dst + e) = make_float4(q[0], q[1], q[2], q[3]);
         }
         __syncthreads();
     }
@@ -1207,7 +1209,7 @@ int fp32_variant_count(int rows, int cols, int)
 int fp32_default_variant(int rows, int cols, int dir)
 {
     if (rows <= 64 && cols <= 64) return 3;
-    if (rows == 128 && cols == 128) return dir == DCT2D_INVERSE ? 0 : 3;
+    if (rows == 128 && cols == 128) return 3;
     return 0;
 }
 
