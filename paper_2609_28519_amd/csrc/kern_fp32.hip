@@ -764,30 +764,9 @@ __device__ __forceinline__ void rows_out(gfloat* dst, float* T, int wid, const f
     }
 }
 
-// The idle stretch of a group (the other group's round): `n` barriers.  With `next` set
-// (the array this workgroup transforms after the current one), the group first issues
-// the loads of that array's first stage half and only consumes them (an empty asm use)
-// after the first barrier, so the reads travel while the other group computes: HBM is
-// otherwise idle during the rounds, and the later real loads of that half then come
-// from the device's caches.
-template <int DIR>
-__device__ __forceinline__ void idle(int n, const gfloat* next, int wid)
-{
-    if (next) {
-        float q[64];
-        if constexpr (DIR == DCT2D_INVERSE) load_rowhalf<0>(next, wid, q); else load_colhalf<0>(next, wid, q);
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 64; ++k) asm volatile("" ::"v"(q[k]));
-        syncs(n - 1);
-    } else {
-        syncs(n);
-    }
-}
-
 // One (group, column half) path of one array.
 template <int DIR, int G, int CR>
-__device__ __forceinline__ void path(const gfloat* src, gfloat* dst, const gfloat* next, float* T, int wid, twptr tw)
+__device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, int wid, twptr tw)
 {
     float R[H];
     if constexpr (DIR == DCT2D_FORWARD) {
@@ -799,9 +778,9 @@ __device__ __forceinline__ void path(const gfloat* src, gfloat* dst, const gfloa
             put_row(T, wid, R);
             __syncthreads();
             col_fwd<CR>(T, wid, o, tw);
-            idle<DIR>(3, next, wid); // round O
+            syncs(3); // round O
         } else {
-            idle<DIR>(3, next, wid); // round E
+            syncs(3); // round E
             put_row(T, wid, R);
             __syncthreads();
             col_fwd<CR>(T, wid, o, tw);
@@ -817,9 +796,9 @@ __device__ __forceinline__ void path(const gfloat* src, gfloat* dst, const gfloa
                 put_halves<CR>(T, wid, R);
                 __syncthreads();
                 row_inv<0>(T, wid, R, tw); // p
-                idle<DIR>(3, next, wid);   // round O
+                syncs(3);                // round O
             } else {
-                idle<DIR>(3, next, wid); // round E
+                syncs(3); // round E
                 put_halves<CR>(T, wid, R);
                 __syncthreads();
                 row_inv<1>(T, wid, R, tw); // q
@@ -842,9 +821,9 @@ __device__ __forceinline__ void path(const gfloat* src, gfloat* dst, const gfloa
                 put_halves<CR>(T, wid, R);
                 __syncthreads();
                 row_inv<0>(T, wid, R, tw); // p
-                idle<DIR>(5, next, wid);   // round O
+                syncs(5);                // round O
             } else {
-                idle<DIR>(5, next, wid); // round E
+                syncs(5); // round E
                 put_row(T, wid, R);
                 __syncthreads();
                 {
@@ -870,7 +849,7 @@ __device__ __forceinline__ void path(const gfloat* src, gfloat* dst, const gfloa
 // array out) fall into each other's compute phases instead of coinciding on every CU.
 template <int DIR>
 __global__ void __launch_bounds__(512, 1)
-k_split256(Addr a, int64_t batch, const float2* __restrict__ tw_in, int stagger, int prefetch)
+k_split256(Addr a, int64_t batch, const float2* __restrict__ tw_in, int stagger)
 {
     using namespace s256;
     __shared__ float4 T4[LDS_FLOATS / 4];
@@ -886,13 +865,12 @@ k_split256(Addr a, int64_t batch, const float2* __restrict__ tw_in, int stagger,
         const twptr tw = per_iteration(tw_in);
         const gfloat* src = uniform_ptr(a.src(blk));
         gfloat* dst = uniform_ptr(a.dst(blk));
-        const gfloat* next = prefetch && blk + gridDim.x < batch ? uniform_ptr(a.src(blk + gridDim.x)) : nullptr;
         if (g == 0) {
-            if (cr == 0) path<DIR, 0, 0>(src, dst, next, T, wid, tw);
-            else path<DIR, 0, 1>(src, dst, next, T, wid, tw);
+            if (cr == 0) path<DIR, 0, 0>(src, dst, T, wid, tw);
+            else path<DIR, 0, 1>(src, dst, T, wid, tw);
         } else {
-            if (cr == 0) path<DIR, 1, 0>(src, dst, next, T, wid, tw);
-            else path<DIR, 1, 1>(src, dst, next, T, wid, tw);
+            if (cr == 0) path<DIR, 1, 0>(src, dst, T, wid, tw);
+            else path<DIR, 1, 1>(src, dst, T, wid, tw);
         }
     }
 }
@@ -1065,13 +1043,11 @@ int launch_split256_dir(const DeviceTables* t, const Job& j)
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_split256<DIR>, 512, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
     // variant 0: one resident workgroup per CU looping over arrays; 2: one array per
-    // workgroup; 3, 4: as 0 with the second cohort started about 3 x 8k / 6 x 8k cycles late;
-    // 5: as 0 with the next array's first half read during the idle rounds
+    // workgroup; 3, 4: as 0 with the second cohort started about 3 x 8k / 6 x 8k cycles late
     const int64_t cap = j.variant == 2 ? ((int64_t)1 << 31) - 1 : (int64_t)t->num_cu * per_cu;
     const unsigned grid = (unsigned)(j.batch < cap ? j.batch : cap);
     const int stagger = j.variant == 3 ? 3 : j.variant == 4 ? 6 : 0;
-    const int prefetch = j.variant >= 5 ? 1 : 0;
-    k_split256<DIR><<<grid, 512, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, 256), stagger, prefetch);
+    k_split256<DIR><<<grid, 512, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, 256), stagger);
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
 }
 
@@ -1191,15 +1167,14 @@ int launch_fused(const DeviceTables* t, const Job& j)
 //   other axes <=128: 0 LDS-staged fused, 1 two-pass
 //   256 x 256:        0 split fused (two groups of wavefronts, two LDS rounds), one
 //                     resident workgroup per CU; 1 two-pass; 2 split fused, one array
-//                     per workgroup; 3, 4 as 0 with the two cohorts of CUs staggered; 5 as
-//                     0 with the next array's first half prefetched during idle rounds
+//                     per workgroup; 3, 4 as 0 with the two cohorts of CUs staggered
 //   other, an axis of 256: 0 two-pass
 int fp32_variant_count(int rows, int cols, int)
 {
     if (rows <= 64 && cols <= 64) return 4;
     if (rows == 128 && cols == 128) return 4;
     if (rows <= 128 && cols <= 128) return 2;
-    if (rows == 256 && cols == 256) return 6;
+    if (rows == 256 && cols == 256) return 5;
     return 1;
 }
 
