@@ -91,6 +91,172 @@ k_dense_pass(Addr a, bool img_is_a, Mat qm, int64_t img_si, int64_t img_sk, int 
     }
 }
 
+// Even/odd form of the same pass for an even length L: Q_L's even rows are symmetric and
+// its odd rows antisymmetric about the middle column (eq. 1), so
+//   forward  Y[2k]   = sum_{n < L/2} Q_L[2k][n]   (x[n] + x[L-1-n])
+//            Y[2k+1] = sum_{n < L/2} Q_L[2k+1][n] (x[n] - x[L-1-n])
+//   inverse  a[n] = sum_{k < L/2} Q_L[2k][n] Y[2k],  b[n] = sum_{k < L/2} Q_L[2k+1][n] Y[2k+1],
+//            x[n] = a[n] + b[n],  x[L-1-n] = a[n] - b[n]
+// i.e. two products of half the depth (half the flops of the dense pass), with the
+// butterflies fused into the operand loads (forward) or the stores (inverse).  A
+// workgroup computes the 64 x 64 tiles of both products for the same output positions,
+// each thread a 4 x 4 micro-tile of each, over K in chunks of 16 with blocked summation.
+// ROW: transform along the rows (length L = cols); else along the columns (L = rows).
+// The source and destination never overlap (the ragged planner ping-pongs through its
+// workspace).
+template <bool ROW, bool INV>
+__global__ void __launch_bounds__(256)
+k_dense_eo(Addr a, const float* __restrict__ q_in, int rows, int cols)
+{
+    __shared__ __attribute__((aligned(16))) float A1[BK][BM + 4];
+    __shared__ __attribute__((aligned(16))) float A2[BK][BM + 4];
+    __shared__ __attribute__((aligned(16))) float B1[BK][BN + 4];
+    __shared__ __attribute__((aligned(16))) float B2[BK][BN + 4];
+    const int t = threadIdx.x;
+    const int z = blockIdx.z;
+    const gfloat* x = a.src(z);
+    gfloat* dst = a.dst(z);
+    const gfloat* q = (const gfloat*)q_in;
+    const int L = ROW ? cols : rows, HL = L / 2;
+    // output tile of the half-size products: ROW: (image row i, half index h); column
+    // pass: (half index h, image column j)
+    const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
+    const int M = ROW ? rows : HL, N = ROW ? HL : cols;
+    const int ti = (t / 16) * 4, tj = (t % 16) * 4;
+    float acc1[4][4] = {}, acc2[4][4] = {};
+    for (int k0 = 0; k0 < HL; k0 += BK) {
+        // ---- operand tiles: A (BM x BK, stored k-major), B (BK x BN) -------------------
+        if (ROW) {
+            // A from the image: rows i0 + r, depth k0 + 4 c4 .. +3 (r = t / 4, c4 = t % 4)
+            const int r = t / 4, c4 = t % 4, gi = i0 + r, gk = k0 + 4 * c4;
+            float4 p1 = make_float4(0.f, 0.f, 0.f, 0.f), p2 = p1;
+            if (gi < rows && gk < HL) {
+                const gfloat* xr = x + (int64_t)gi * cols;
+                if (!INV) {
+                    const float4 lo = *reinterpret_cast<const gfloat4*>(xr + gk);
+                    const float4 hi = *reinterpret_cast<const gfloat4*>(xr + L - 4 - gk); // x[L-1-gk-3 .. L-1-gk]
+                    p1 = make_float4(lo.x + hi.w, lo.y + hi.z, lo.z + hi.y, lo.w + hi.x);
+                    p2 = make_float4(lo.x - hi.w, lo.y - hi.z, lo.z - hi.y, lo.w - hi.x);
+                } else {
+                    const float4 e0 = *reinterpret_cast<const gfloat4*>(xr + 2 * gk);     // Y[2gk .. 2gk+3]
+                    const float4 e1 = *reinterpret_cast<const gfloat4*>(xr + 2 * gk + 4); // Y[2gk+4 .. 2gk+7]
+                    p1 = make_float4(e0.x, e0.z, e1.x, e1.z);
+                    p2 = make_float4(e0.y, e0.w, e1.y, e1.w);
+                }
+            }
+            A1[4 * c4][r] = p1.x; A1[4 * c4 + 1][r] = p1.y; A1[4 * c4 + 2][r] = p1.z; A1[4 * c4 + 3][r] = p1.w;
+            A2[4 * c4][r] = p2.x; A2[4 * c4 + 1][r] = p2.y; A2[4 * c4 + 2][r] = p2.z; A2[4 * c4 + 3][r] = p2.w;
+            // B from Q_L: B1(k, h) = Q[2h][k] (forward) or Q[2k][h] (inverse); B2 with 2h+1 / 2k+1
+            if (!INV) {
+                const int h = t / 4, c = 4 * (t % 4), gh = j0 + h, gk2 = k0 + c;
+                float4 b1 = make_float4(0.f, 0.f, 0.f, 0.f), b2 = b1;
+                if (gh < HL && gk2 < HL) {
+                    b1 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gh) * L + gk2);
+                    b2 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gh + 1) * L + gk2);
+                }
+                B1[c][h] = b1.x; B1[c + 1][h] = b1.y; B1[c + 2][h] = b1.z; B1[c + 3][h] = b1.w;
+                B2[c][h] = b2.x; B2[c + 1][h] = b2.y; B2[c + 2][h] = b2.z; B2[c + 3][h] = b2.w;
+            } else {
+                const int k = t / 16, c = 4 * (t % 16), gk2 = k0 + k, gh = j0 + c;
+                float4 b1 = make_float4(0.f, 0.f, 0.f, 0.f), b2 = b1;
+                if (gk2 < HL && gh < HL) {
+                    b1 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gk2) * L + gh);
+                    b2 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gk2 + 1) * L + gh);
+                }
+                *reinterpret_cast<float4*>(&B1[k][c]) = b1;
+                *reinterpret_cast<float4*>(&B2[k][c]) = b2;
+            }
+        } else {
+            // A from Q_L: A1(h, k) = Q[2h][k] (forward) or Q[2k][h] (inverse); A2 with 2h+1 / 2k+1
+            if (!INV) {
+                const int h = t / 4, c = 4 * (t % 4), gh = i0 + h, gk = k0 + c;
+                float4 a1 = make_float4(0.f, 0.f, 0.f, 0.f), a2 = a1;
+                if (gh < HL && gk < HL) {
+                    a1 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gh) * L + gk);
+                    a2 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gh + 1) * L + gk);
+                }
+                A1[c][h] = a1.x; A1[c + 1][h] = a1.y; A1[c + 2][h] = a1.z; A1[c + 3][h] = a1.w;
+                A2[c][h] = a2.x; A2[c + 1][h] = a2.y; A2[c + 2][h] = a2.z; A2[c + 3][h] = a2.w;
+            } else {
+                const int k = t / 16, c = 4 * (t % 16), gk = k0 + k, gh = i0 + c;
+                float4 a1 = make_float4(0.f, 0.f, 0.f, 0.f), a2 = a1;
+                if (gk < HL && gh < HL) {
+                    a1 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gk) * L + gh);
+                    a2 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gk + 1) * L + gh);
+                }
+                *reinterpret_cast<float4*>(&A1[k][c]) = a1;
+                *reinterpret_cast<float4*>(&A2[k][c]) = a2;
+            }
+            // B from the image: depth rows k0 + k (k = t / 16), columns j0 + 4 (t % 16) .. +3
+            const int k = t / 16, c = 4 * (t % 16), gk = k0 + k, gj = j0 + c;
+            float4 p1 = make_float4(0.f, 0.f, 0.f, 0.f), p2 = p1;
+            if (gk < HL && gj < cols) {
+                if (!INV) {
+                    const float4 lo = *reinterpret_cast<const gfloat4*>(x + (int64_t)gk * cols + gj);
+                    const float4 hi = *reinterpret_cast<const gfloat4*>(x + (int64_t)(L - 1 - gk) * cols + gj);
+                    p1 = make_float4(lo.x + hi.x, lo.y + hi.y, lo.z + hi.z, lo.w + hi.w);
+                    p2 = make_float4(lo.x - hi.x, lo.y - hi.y, lo.z - hi.z, lo.w - hi.w);
+                } else {
+                    p1 = *reinterpret_cast<const gfloat4*>(x + (int64_t)(2 * gk) * cols + gj);
+                    p2 = *reinterpret_cast<const gfloat4*>(x + (int64_t)(2 * gk + 1) * cols + gj);
+                }
+            }
+            *reinterpret_cast<float4*>(&B1[k][c]) = p1;
+            *reinterpret_cast<float4*>(&B2[k][c]) = p2;
+        }
+        __syncthreads();
+        float part1[4][4] = {}, part2[4][4] = {};
+#pragma unroll
+        for (int k = 0; k < BK; ++k) {
+            const float4 av1 = *reinterpret_cast<const float4*>(&A1[k][ti]);
+            const float4 av2 = *reinterpret_cast<const float4*>(&A2[k][ti]);
+            const float4 bv1 = *reinterpret_cast<const float4*>(&B1[k][tj]);
+            const float4 bv2 = *reinterpret_cast<const float4*>(&B2[k][tj]);
+            const float a1[4] = {av1.x, av1.y, av1.z, av1.w}, a2[4] = {av2.x, av2.y, av2.z, av2.w};
+            const float b1[4] = {bv1.x, bv1.y, bv1.z, bv1.w}, b2[4] = {bv2.x, bv2.y, bv2.z, bv2.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    part1[u][v] = fmaf(a1[u], b1[v], part1[u][v]);
+                    part2[u][v] = fmaf(a2[u], b2[v], part2[u][v]);
+                }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                acc1[u][v] += part1[u][v];
+                acc2[u][v] += part2[u][v];
+            }
+        __syncthreads();
+    }
+    // ---- stores: interleave (forward) or recombine (inverse) ------------------------------
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int gi = i0 + ti + u;
+        if (gi >= M) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int gj = j0 + tj + v;
+            if (gj >= N) continue;
+            if (ROW) {
+                gfloat* dr = dst + (int64_t)gi * cols;
+                if (!INV) { dr[2 * gj] = acc1[u][v]; dr[2 * gj + 1] = acc2[u][v]; }
+                else { dr[gj] = acc1[u][v] + acc2[u][v]; dr[L - 1 - gj] = acc1[u][v] - acc2[u][v]; }
+            } else {
+                if (!INV) {
+                    dst[(int64_t)(2 * gi) * cols + gj] = acc1[u][v];
+                    dst[(int64_t)(2 * gi + 1) * cols + gj] = acc2[u][v];
+                } else {
+                    dst[(int64_t)gi * cols + gj] = acc1[u][v] + acc2[u][v];
+                    dst[(int64_t)(L - 1 - gi) * cols + gj] = acc1[u][v] - acc2[u][v];
+                }
+            }
+        }
+    }
+}
+
 } // namespace
 
 // One axis pass over `count` images of rows x cols.  q: dense Q_L (L = rows for a column
@@ -101,6 +267,21 @@ int launch_dense_axis(const Addr& a, int64_t count, int rows, int cols, bool col
 {
     if (count <= 0) return DCT2D_OK;
     if (count > 65535) return DCT2D_ERR_ARG;
+    const int L = column_pass ? rows : cols;
+    if (L % 8 == 0) {
+        // even/odd form (half the flops); needs L / 2 divisible by 4 for the 16-byte loads
+        const int HL = L / 2;
+        const dim3 grid = column_pass ? dim3((cols + BN - 1) / BN, (HL + BM - 1) / BM, (unsigned)count)
+                                      : dim3((HL + BN - 1) / BN, (rows + BM - 1) / BM, (unsigned)count);
+        if (column_pass) {
+            if (inverse) k_dense_eo<false, true><<<grid, 256, 0, s>>>(a, q, rows, cols);
+            else k_dense_eo<false, false><<<grid, 256, 0, s>>>(a, q, rows, cols);
+        } else {
+            if (inverse) k_dense_eo<true, true><<<grid, 256, 0, s>>>(a, q, rows, cols);
+            else k_dense_eo<true, false><<<grid, 256, 0, s>>>(a, q, rows, cols);
+        }
+        return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
+    }
     int M, N, K;
     Mat qm;
     bool img_is_a;

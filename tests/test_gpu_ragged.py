@@ -44,7 +44,9 @@ def _check(rg: workloads.Ragged, out: np.ndarray, direction: str, idx=None, labe
 
 
 def _small_ragged(seed=11):
-    images = ((1024, 1024), (512, 384), (384, 512), (256, 128), (64, 1024))
+    # image axes: even/odd dense passes (1024, 512, 384, 64, 40, 24) and the plain dense
+    # pass (12, 20: half-lengths not multiples of 4)
+    images = ((1024, 1024), (512, 384), (384, 512), (256, 128), (64, 1024), (40, 24), (12, 20))
     return workloads.c4_ragged(blocks=3000, images=images, seed=seed)
 
 
