@@ -243,8 +243,9 @@ def kernel_name(n, d, tuned):
     if path != "fp32":
         return None
     if n <= 64:
-        return {0: "k_wave<%d, %d, %d>", 3: "k_wave<%d, %d, %d>", 1: "k_fused<%d, %d, %d>"}.get(v, "") % (n, n, di) \
-            if v in (0, 1, 3) else None
+        if v in (0, 3, 4):
+            return "k_wave<%d, %d, %d, %s>" % (n, n, di, "true" if v == 4 else "false")
+        return "k_fused<%d, %d, %d>" % (n, n, di) if v == 1 else None
     if n == 128:
         if v in (0, 3):
             return "k_split128<%d, %s>" % (di, "true" if v == 3 else "false")

@@ -93,6 +93,23 @@ struct Addr {
         float* base = out_slot ? *(gfloat* const DCT_GLOBAL*)out_slot : out;
         return (gfloat*)base + (out_idx ? ((const DCT_GLOBAL int64_t*)out_idx)[b] : b * out_stride);
     }
+    // the two parts of src / dst, for callers that resolve several arrays at once
+    __device__ __forceinline__ const gfloat* src_base() const
+    {
+        return (const gfloat*)(in_slot ? *(const gfloat* const DCT_GLOBAL*)in_slot : in);
+    }
+    __device__ __forceinline__ int64_t src_off(int64_t b) const
+    {
+        return in_idx ? ((const DCT_GLOBAL int64_t*)in_idx)[b] : b * in_stride;
+    }
+    __device__ __forceinline__ gfloat* dst_base() const
+    {
+        return (gfloat*)(out_slot ? *(gfloat* const DCT_GLOBAL*)out_slot : out);
+    }
+    __device__ __forceinline__ int64_t dst_off(int64_t b) const
+    {
+        return out_idx ? ((const DCT_GLOBAL int64_t*)out_idx)[b] : b * out_stride;
+    }
 };
 
 // ---- kernel launchers (each returns a DCT2D_* status) ------------------------------

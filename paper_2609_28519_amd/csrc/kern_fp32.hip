@@ -164,7 +164,113 @@ struct WaveCfg {
     static constexpr int LDS_FLOATS = BPW * BS;
 };
 
-template <int H, int W, int DIR>
+// Row tl of array b from HBM into registers (zeros for a tail slot past the batch).
+template <int H, int W>
+__device__ __forceinline__ void wave_rows_in(float (&v)[W], const Addr& a, int64_t b, bool valid, int tl)
+{
+    if (valid) {
+        const gfloat* src = a.src(b) + (int64_t)tl * W;
+#pragma unroll
+        for (int j = 0; j < W / 4; ++j) {
+            const float4 q = *reinterpret_cast<const gfloat4*>(src + 4 * j);
+            v[4 * j] = q.x; v[4 * j + 1] = q.y; v[4 * j + 2] = q.z; v[4 * j + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < W; ++j) v[j] = 0.f;
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void lds_row_in(float (&v)[W], const float* row)
+{
+#pragma unroll
+    for (int j = 0; j < W / 4; ++j) {
+        const float4 q = *reinterpret_cast<const float4*>(row + 4 * j);
+        v[4 * j] = q.x; v[4 * j + 1] = q.y; v[4 * j + 2] = q.z; v[4 * j + 3] = q.w;
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void lds_row_out(float* row, const float (&v)[W])
+{
+#pragma unroll
+    for (int j = 0; j < W / 4; ++j)
+        *reinterpret_cast<float4*>(row + 4 * j) = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+}
+
+// Whole-tile moves between HBM and the wavefront's LDS tile: the BPW arrays of the tile
+// as 16-byte chunks, consecutive lanes on consecutive chunks of an array (each wavefront
+// instruction covers 1 KB of one array, or whole arrays when they are smaller).
+// Chunk 64 i + t of a wavefront's tile: array bb of the tile, 16-byte chunk q of that array.
+// Arrays of 64 chunks or more: one array per instruction (bb known at compile time);
+// smaller arrays: 64 / CPB whole arrays per instruction.
+template <int H, int W>
+struct WaveChunks {
+    using C = WaveCfg<H, W>;
+    static constexpr int CPB = H * W / 4, CH = CPB * C::BPW, NI = CH / 64;
+    static constexpr bool WIDE = CPB >= 64;
+    static constexpr int NA = WIDE ? C::BPW : NI; // distinct arrays a lane touches
+    static_assert(CH % 64 == 0 && (CPB % 64 == 0 || 64 % CPB == 0), "whole wavefront instructions");
+    __device__ static int array(int i, int t) { return WIDE ? (64 * i) / CPB : (64 * i) / CPB + t / CPB; }
+    __device__ static int chunk(int i, int t) { return WIDE ? (64 * i) % CPB + t : t % CPB; }
+    __device__ static int slot(int i) { return WIDE ? (64 * i) / CPB : i; } // index into the NA arrays
+    __device__ static int lds_off(int i, int t)
+    {
+        const int q = chunk(i, t);
+        return array(i, t) * C::BS + (q / (W / 4)) * C::P + 4 * (q % (W / 4));
+    }
+};
+
+// Whole-tile moves between HBM and the wavefront's LDS tile (consecutive lanes on
+// consecutive 16-byte chunks).  Array addresses are resolved once, before the first
+// access: an offset-list or base-slot read issued after a store would wait for it.
+template <int H, int W>
+__device__ __forceinline__ void wave_tile_in(float* lds, const Addr& a, int64_t b0, int64_t batch, int t)
+{
+    using K = WaveChunks<H, W>;
+    const gfloat* base = a.src_base();
+    const gfloat* p[K::NA];
+#pragma unroll
+    for (int k = 0; k < K::NA; ++k) {
+        const int64_t b = b0 + (K::WIDE ? k : K::array(k, t));
+        // a tail slot past the batch transforms a copy of array b0 (always in the batch)
+        // and is never stored, so every load is unconditional and all are in flight at once
+        p[k] = base + a.src_off(b < batch ? b : b0);
+    }
+#pragma unroll
+    for (int i = 0; i < K::NI; ++i) {
+        const float4 v = *reinterpret_cast<const gfloat4*>(p[K::slot(i)] + 4 * K::chunk(i, t));
+        *reinterpret_cast<float4*>(lds + K::lds_off(i, t)) = v;
+    }
+}
+
+template <int H, int W>
+__device__ __forceinline__ void wave_tile_out(const float* lds, const Addr& a, int64_t b0, int64_t batch, int t)
+{
+    using K = WaveChunks<H, W>;
+    gfloat* base = a.dst_base();
+    gfloat* p[K::NA];
+    bool ok[K::NA]; // wave-uniform when WIDE
+#pragma unroll
+    for (int k = 0; k < K::NA; ++k) {
+        const int64_t b = b0 + (K::WIDE ? k : K::array(k, t));
+        ok[k] = b < batch;
+        p[k] = base + a.dst_off(ok[k] ? b : b0);
+        asm volatile("" : "+v"(p[k])); // materialised here, not sunk between the stores
+    }
+#pragma unroll
+    for (int i = 0; i < K::NI; ++i) {
+        const float4 v = *reinterpret_cast<const float4*>(lds + K::lds_off(i, t));
+        if (ok[K::slot(i)]) *reinterpret_cast<gfloat4*>(p[K::slot(i)] + 4 * K::chunk(i, t)) = v;
+    }
+}
+
+// Wave-local kernel.  Plain: each lane loads its row from HBM and the results leave from
+// registers (columns as 4-byte stores across the lanes, round-trip rows as 16-byte row
+// stores).  STAGE: the tile enters and leaves through the LDS tile with whole-tile
+// coalesced 16-byte moves, and the lanes read and write their rows and columns there.
+template <int H, int W, int DIR, bool STAGE>
 __global__ void __launch_bounds__(64)
 k_wave(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* __restrict__ tww_in)
 {
@@ -176,66 +282,58 @@ k_wave(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* _
     const int64_t ntiles = (batch + C::BPW - 1) / C::BPW;
     float* tile_lds = lds + tb * C::BS;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        twptr twh = per_iteration(twh_in);
-        twptr tww = per_iteration(tww_in);
-        const int64_t b = tile * C::BPW + tb;
+        const int64_t b0 = tile * C::BPW;
+        const int64_t b = b0 + tb;
         const bool valid = b < batch;
+        if (STAGE) {
+            wave_tile_in<H, W>(lds, a, b0, batch, t);
+            __syncthreads();
+        }
+        twptr tww = per_iteration(tww_in);
         if (tl < H) {
             float v[W];
-            if (valid) {
-                const gfloat* src = a.src(b) + (int64_t)tl * W;
-#pragma unroll
-                for (int j = 0; j < W / 4; ++j) {
-                    const float4 q = *reinterpret_cast<const gfloat4*>(src + 4 * j);
-                    v[4 * j] = q.x; v[4 * j + 1] = q.y; v[4 * j + 2] = q.z; v[4 * j + 3] = q.w;
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < W; ++j) v[j] = 0.f;
-            }
+            if (STAGE) lds_row_in<W>(v, tile_lds + tl * C::P); else wave_rows_in<H, W>(v, a, b, valid, tl);
             if (DIR == DCT2D_INVERSE) dct3_ortho<W>(v, tww); else dct2_ortho<W>(v, tww);
-            float* row = tile_lds + tl * C::P;
-#pragma unroll
-            for (int j = 0; j < W / 4; ++j)
-                *reinterpret_cast<float4*>(row + 4 * j) = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+            lds_row_out<W>(tile_lds + tl * C::P, v);
         }
         __syncthreads();
-        twh = per_iteration(twh_in); // the column pass re-reads its twiddles (see per_iteration)
+        twptr twh = per_iteration(twh_in); // the column pass re-reads its twiddles (see per_iteration)
         if (tl < W) {
-            float v[H];
+            float c[H];
             float* col = tile_lds + tl;
 #pragma unroll
-            for (int r = 0; r < H; ++r) v[r] = col[r * C::P];
-            apply1d<H, DIR>(v, twh);
-            if (DIR == DCT2D_ROUNDTRIP) {
+            for (int r = 0; r < H; ++r) c[r] = col[r * C::P];
+            apply1d<H, DIR>(c, twh);
+            if (STAGE || DIR == DCT2D_ROUNDTRIP) {
 #pragma unroll
-                for (int r = 0; r < H; ++r) col[r * C::P] = v[r];
+                for (int r = 0; r < H; ++r) col[r * C::P] = c[r];
             } else if (valid) {
                 gfloat* dst = a.dst(b) + tl;
 #pragma unroll
-                for (int r = 0; r < H; ++r) dst[(int64_t)r * W] = v[r];
+                for (int r = 0; r < H; ++r) dst[(int64_t)r * W] = c[r];
             }
         }
         if (DIR == DCT2D_ROUNDTRIP) {
             __syncthreads();
             tww = per_iteration(tww_in);
             if (tl < H) {
-                float v[W];
-                const float* row = tile_lds + tl * C::P;
-#pragma unroll
-                for (int j = 0; j < W / 4; ++j) {
-                    const float4 q = *reinterpret_cast<const float4*>(row + 4 * j);
-                    v[4 * j] = q.x; v[4 * j + 1] = q.y; v[4 * j + 2] = q.z; v[4 * j + 3] = q.w;
-                }
-                dct3_ortho<W>(v, tww);
-                if (valid) {
+                float r[W];
+                lds_row_in<W>(r, tile_lds + tl * C::P);
+                dct3_ortho<W>(r, tww);
+                if (STAGE) {
+                    lds_row_out<W>(tile_lds + tl * C::P, r);
+                } else if (valid) {
                     gfloat* dst = a.dst(b) + (int64_t)tl * W;
 #pragma unroll
                     for (int j = 0; j < W / 4; ++j)
                         *reinterpret_cast<gfloat4*>(dst + 4 * j) =
-                            make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+                            make_float4(r[4 * j], r[4 * j + 1], r[4 * j + 2], r[4 * j + 3]);
                 }
             }
+        }
+        if (STAGE) {
+            __syncthreads();
+            wave_tile_out<H, W>(lds, a, b0, batch, t);
         }
         __syncthreads();
     }
@@ -957,34 +1055,40 @@ int launch_fused_hw(const DeviceTables* t, const Job& j)
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
 }
 
-template <int H, int W, int DIR>
+template <int H, int W, int DIR, bool STAGE>
 int launch_wave_dir(const DeviceTables* t, const Job& j)
 {
     using C = WaveCfg<H, W>;
     const int64_t ntiles = (j.batch + C::BPW - 1) / C::BPW;
     int64_t cap;
-    if (j.variant == 3) {
+    if (j.variant >= 3) {
         cap = (int64_t)1 << 30; // one tile per workgroup (no grid-stride reuse)
     } else {
         int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wave<H, W, DIR>, 64, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wave<H, W, DIR, STAGE>, 64, 0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
         cap = (int64_t)t->num_cu * per_cu * 4;
     }
     const unsigned grid = (unsigned)(ntiles < cap ? ntiles : cap);
-    k_wave<H, W, DIR><<<grid, 64, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, H), tw_for(t, W));
+    k_wave<H, W, DIR, STAGE><<<grid, 64, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, H), tw_for(t, W));
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
+}
+
+template <int H, int W, bool STAGE>
+int launch_wave_stage(const DeviceTables* t, const Job& j)
+{
+    switch (j.dir) {
+    case DCT2D_FORWARD: return launch_wave_dir<H, W, DCT2D_FORWARD, STAGE>(t, j);
+    case DCT2D_INVERSE: return launch_wave_dir<H, W, DCT2D_INVERSE, STAGE>(t, j);
+    default: return launch_wave_dir<H, W, DCT2D_ROUNDTRIP, STAGE>(t, j);
+    }
 }
 
 template <int H, int W>
 int launch_wave_hw(const DeviceTables* t, const Job& j)
 {
-    switch (j.dir) {
-    case DCT2D_FORWARD: return launch_wave_dir<H, W, DCT2D_FORWARD>(t, j);
-    case DCT2D_INVERSE: return launch_wave_dir<H, W, DCT2D_INVERSE>(t, j);
-    default: return launch_wave_dir<H, W, DCT2D_ROUNDTRIP>(t, j);
-    }
+    return j.variant == 4 ? launch_wave_stage<H, W, true>(t, j) : launch_wave_stage<H, W, false>(t, j);
 }
 
 template <int H>
@@ -1160,7 +1264,8 @@ int launch_fused(const DeviceTables* t, const Job& j)
 
 // Variants (frozen per size by the policy table / autotuner):
 //   both axes <= 64:  0 wave-local fused, 1 LDS-staged fused, 2 two-pass,
-//                     3 wave-local fused with one tile per workgroup
+//                     3 wave-local fused with one tile per workgroup, 4 as 3 with the
+//                     tile staged through LDS by coalesced 16-byte loads and stores
 //   128 x 128:        0 split fused (two wavefronts per transform), 1 LDS-staged fused, 2 two-pass,
 //                     3 split fused with the rows (inverse: columns) read through an LDS copy
 //                     of the array
@@ -1171,7 +1276,7 @@ int launch_fused(const DeviceTables* t, const Job& j)
 //   other, an axis of 256: 0 two-pass
 int fp32_variant_count(int rows, int cols, int)
 {
-    if (rows <= 64 && cols <= 64) return 4;
+    if (rows <= 64 && cols <= 64) return 5;
     if (rows == 128 && cols == 128) return 4;
     if (rows <= 128 && cols <= 128) return 2;
     if (rows == 256 && cols == 256) return 5;
@@ -1179,11 +1284,12 @@ int fp32_variant_count(int rows, int cols, int)
 }
 
 // Variant used until the tuner measures otherwise (fastest in measurements on MI355X
-// with 512 MiB batches): wave-local with one tile per workgroup for axes <= 64, the
-// staged split kernel for 128 x 128, the split kernel for 256 x 256.
+// with 512 MiB batches): for axes <= 64 the staged wave-local kernel for round trips and
+// for axes <= 16, else the plain one (one tile per workgroup); the staged split kernel
+// for 128 x 128, the split kernel for 256 x 256.
 int fp32_default_variant(int rows, int cols, int dir)
 {
-    if (rows <= 64 && cols <= 64) return 3;
+    if (rows <= 64 && cols <= 64) return dir == DCT2D_ROUNDTRIP || (rows <= 16 && cols <= 16) ? 4 : 3;
     if (rows == 128 && cols == 128) return 3;
     return 0;
 }
@@ -1191,7 +1297,7 @@ int fp32_default_variant(int rows, int cols, int dir)
 int launch_fp32(const DeviceTables* t, const Job& j)
 {
     if (j.rows <= 64 && j.cols <= 64) {
-        if (j.variant == 0 || j.variant == 3) return launch_wave(t, j);
+        if (j.variant == 0 || j.variant == 3 || j.variant == 4) return launch_wave(t, j);
         if (j.variant == 1) return launch_fused(t, j);
         return launch_two_pass(t, j);
     }

@@ -205,3 +205,34 @@ def test_every_variant(h, w, direction):
             assert_parity(x, run(x, direction), direction, label="%dx%d v%d" % (h, w, v))
     finally:
         dct.set_variant(h, w, direction, "fp32", keep)
+
+
+@pytest.mark.parametrize("h,w", [(8, 8), (16, 16), (32, 32), (64, 64), (8, 64), (64, 16)])
+@pytest.mark.parametrize("direction", DIRS)
+def test_wave_variants_many_tiles(h, w, direction):
+    """The wave-local variants (0: grid-stride over several tiles per workgroup, 4: tiles
+    staged through LDS with whole-tile 16-byte moves) on a 64 MiB batch plus a ragged tail;
+    about 500 sampled arrays (the first, the last and the tail among them) are checked."""
+    import torch
+    dct = _lib()
+    batch = (1 << 24) // (h * w) + 5
+    g = np.random.default_rng(7 * h + w)
+    x = g.standard_normal((batch, h, w)).astype(np.float32)
+    idx = np.unique(np.concatenate([g.integers(0, batch, 500), np.arange(batch - 6, batch), [0]]))
+    xs = x[idx].copy()
+    ref = oracle.forward(xs) if direction == "forward" else oracle.inverse(xs) if direction == "inverse" else xs
+    keep = dct.get_variant(h, w, direction, "fp32")
+    t = torch.from_numpy(x).cuda()
+    out = torch.empty_like(t)
+    try:
+        for v in (0, 4):
+            dct.set_variant(h, w, direction, "fp32", v)
+            out.fill_(float("nan"))
+            dct.transform(t, out, direction, "fp32")
+            torch.cuda.synchronize()
+            y = out[torch.from_numpy(idx).cuda()].cpu().numpy()
+            e = oracle.e_rel(y, ref, xs)
+            assert np.isfinite(e).all() and e.max() <= GATE[direction], "%dx%d v%d %s: %.3e" % (
+                h, w, v, direction, e.max())
+    finally:
+        dct.set_variant(h, w, direction, "fp32", keep)
