@@ -243,8 +243,9 @@ def kernel_name(n, d, tuned):
     if path != "fp32":
         return None
     if n <= 64:
-        if v in (0, 3, 4):
-            return "k_wave<%d, %d, %d, %s>" % (n, n, di, "true" if v == 4 else "false")
+        if v == 0 or v >= 3:
+            stage = v == 4 or (v >= 5 and (v - 5) % 2 == 1)
+            return "k_wave<%d, %d, %d, %s>" % (n, n, di, "true" if stage else "false")
         return "k_fused<%d, %d, %d>" % (n, n, di) if v == 1 else None
     if n == 128:
         if v in (0, 3):

@@ -158,10 +158,26 @@ struct WaveCfg {
     static constexpr int TB = cmax(H, W);
     static_assert(TB <= 64, "one wavefront per tile");
     static constexpr int BPW = 64 / TB;
-    static constexpr int P = W + 4;
+    // Rows of 16 or more floats are stored unpadded, with the 16-byte groups of row r
+    // XOR-permuted by a row key: the 16 rows that one 16-lane phase of a lane-per-row
+    // 16-byte access touches land on 16 different group positions of the 64 banks, a
+    // lane-per-column 4-byte access reads a permutation of one row, and an array takes
+    // exactly H*W floats (which raises the number of resident workgroups where LDS is the
+    // limit).  Rows of 8 use the padded pitch 12.
+    static constexpr bool SWZ = W >= 16;
+    static constexpr int G = W / 4;                  // 16-byte groups per row
+    static constexpr int RPL = W >= 64 ? 1 : 64 / W; // rows per 64-bank line
+    static constexpr int P = SWZ ? W : W + 4;
     static constexpr int HP = H * P;
+    // array pitch: the arrays of one wavefront start in different banks
     static constexpr int BS = TB >= 64 ? HP : HP + ((TB - HP % 64) + 64) % 64;
     static constexpr int LDS_FLOATS = BPW * BS;
+    // float offset of group j of row r, and of element (r, c)
+    __device__ static int at4(int r, int j)
+    {
+        return SWZ ? r * P + 4 * (j ^ ((r / RPL) & (G - 1))) : r * P + 4 * j;
+    }
+    __device__ static int at(int r, int c) { return at4(r, c >> 2) + (c & 3); }
 };
 
 // Row tl of array b from HBM into registers (zeros for a tail slot past the batch).
@@ -181,27 +197,26 @@ __device__ __forceinline__ void wave_rows_in(float (&v)[W], const Addr& a, int64
     }
 }
 
-template <int W>
-__device__ __forceinline__ void lds_row_in(float (&v)[W], const float* row)
+template <int H, int W>
+__device__ __forceinline__ void lds_row_in(float (&v)[W], const float* tile, int r)
 {
+    using C = WaveCfg<H, W>;
 #pragma unroll
     for (int j = 0; j < W / 4; ++j) {
-        const float4 q = *reinterpret_cast<const float4*>(row + 4 * j);
+        const float4 q = *reinterpret_cast<const float4*>(tile + C::at4(r, j));
         v[4 * j] = q.x; v[4 * j + 1] = q.y; v[4 * j + 2] = q.z; v[4 * j + 3] = q.w;
     }
 }
 
-template <int W>
-__device__ __forceinline__ void lds_row_out(float* row, const float (&v)[W])
+template <int H, int W>
+__device__ __forceinline__ void lds_row_out(float* tile, int r, const float (&v)[W])
 {
+    using C = WaveCfg<H, W>;
 #pragma unroll
     for (int j = 0; j < W / 4; ++j)
-        *reinterpret_cast<float4*>(row + 4 * j) = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+        *reinterpret_cast<float4*>(tile + C::at4(r, j)) = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
 }
 
-// Whole-tile moves between HBM and the wavefront's LDS tile: the BPW arrays of the tile
-// as 16-byte chunks, consecutive lanes on consecutive chunks of an array (each wavefront
-// instruction covers 1 KB of one array, or whole arrays when they are smaller).
 // Chunk 64 i + t of a wavefront's tile: array bb of the tile, 16-byte chunk q of that array.
 // Arrays of 64 chunks or more: one array per instruction (bb known at compile time);
 // smaller arrays: 64 / CPB whole arrays per instruction.
@@ -218,7 +233,7 @@ struct WaveChunks {
     __device__ static int lds_off(int i, int t)
     {
         const int q = chunk(i, t);
-        return array(i, t) * C::BS + (q / (W / 4)) * C::P + 4 * (q % (W / 4));
+        return array(i, t) * C::BS + C::at4(q / (W / 4), q % (W / 4));
     }
 };
 
@@ -292,21 +307,20 @@ k_wave(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* _
         twptr tww = per_iteration(tww_in);
         if (tl < H) {
             float v[W];
-            if (STAGE) lds_row_in<W>(v, tile_lds + tl * C::P); else wave_rows_in<H, W>(v, a, b, valid, tl);
+            if (STAGE) lds_row_in<H, W>(v, tile_lds, tl); else wave_rows_in<H, W>(v, a, b, valid, tl);
             if (DIR == DCT2D_INVERSE) dct3_ortho<W>(v, tww); else dct2_ortho<W>(v, tww);
-            lds_row_out<W>(tile_lds + tl * C::P, v);
+            lds_row_out<H, W>(tile_lds, tl, v);
         }
         __syncthreads();
         twptr twh = per_iteration(twh_in); // the column pass re-reads its twiddles (see per_iteration)
         if (tl < W) {
             float c[H];
-            float* col = tile_lds + tl;
 #pragma unroll
-            for (int r = 0; r < H; ++r) c[r] = col[r * C::P];
+            for (int r = 0; r < H; ++r) c[r] = tile_lds[C::at(r, tl)];
             apply1d<H, DIR>(c, twh);
             if (STAGE || DIR == DCT2D_ROUNDTRIP) {
 #pragma unroll
-                for (int r = 0; r < H; ++r) col[r * C::P] = c[r];
+                for (int r = 0; r < H; ++r) tile_lds[C::at(r, tl)] = c[r];
             } else if (valid) {
                 gfloat* dst = a.dst(b) + tl;
 #pragma unroll
@@ -318,10 +332,10 @@ k_wave(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* _
             tww = per_iteration(tww_in);
             if (tl < H) {
                 float r[W];
-                lds_row_in<W>(r, tile_lds + tl * C::P);
+                lds_row_in<H, W>(r, tile_lds, tl);
                 dct3_ortho<W>(r, tww);
                 if (STAGE) {
-                    lds_row_out<W>(tile_lds + tl * C::P, r);
+                    lds_row_out<H, W>(tile_lds, tl, r);
                 } else if (valid) {
                     gfloat* dst = a.dst(b) + (int64_t)tl * W;
 #pragma unroll
@@ -1055,14 +1069,26 @@ int launch_fused_hw(const DeviceTables* t, const Job& j)
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
 }
 
+// Workgroups per CU that the occupancy-capped wave variants allow (5 + 2 k and 6 + 2 k use
+// cap k).  Fewer resident tiles keep fewer bytes in flight per CU; on MI355X a plain
+// in-place tile copy through LDS moves 6.1 TB/s with about 40 KB in flight per CU and
+// 5.4 TB/s with 160 KB, so the cap is a tuning dimension of its own.
+constexpr int kWaveCaps[4] = {16, 10, 6, 4};
+
 template <int H, int W, int DIR, bool STAGE>
 int launch_wave_dir(const DeviceTables* t, const Job& j)
 {
     using C = WaveCfg<H, W>;
     const int64_t ntiles = (j.batch + C::BPW - 1) / C::BPW;
     int64_t cap;
+    size_t reserve = 0; // dynamic LDS that only limits residency
     if (j.variant >= 3) {
         cap = (int64_t)1 << 30; // one tile per workgroup (no grid-stride reuse)
+        if (j.variant >= 5) {
+            const size_t per_wg = (size_t)(160 * 1024 / kWaveCaps[(j.variant - 5) >> 1]) & ~(size_t)255;
+            const size_t have = sizeof(float) * ((C::LDS_FLOATS + 3) / 4 * 4);
+            reserve = per_wg > have ? per_wg - have : 0;
+        }
     } else {
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_wave<H, W, DIR, STAGE>, 64, 0) != hipSuccess ||
@@ -1071,7 +1097,7 @@ int launch_wave_dir(const DeviceTables* t, const Job& j)
         cap = (int64_t)t->num_cu * per_cu * 4;
     }
     const unsigned grid = (unsigned)(ntiles < cap ? ntiles : cap);
-    k_wave<H, W, DIR, STAGE><<<grid, 64, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, H), tw_for(t, W));
+    k_wave<H, W, DIR, STAGE><<<grid, 64, reserve, j.stream>>>(j.addr(), j.batch, tw_for(t, H), tw_for(t, W));
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
 }
 
@@ -1088,7 +1114,8 @@ int launch_wave_stage(const DeviceTables* t, const Job& j)
 template <int H, int W>
 int launch_wave_hw(const DeviceTables* t, const Job& j)
 {
-    return j.variant == 4 ? launch_wave_stage<H, W, true>(t, j) : launch_wave_stage<H, W, false>(t, j);
+    const bool stage = j.variant == 4 || (j.variant >= 5 && ((j.variant - 5) & 1));
+    return stage ? launch_wave_stage<H, W, true>(t, j) : launch_wave_stage<H, W, false>(t, j);
 }
 
 template <int H>
@@ -1265,7 +1292,9 @@ int launch_fused(const DeviceTables* t, const Job& j)
 // Variants (frozen per size by the policy table / autotuner):
 //   both axes <= 64:  0 wave-local fused, 1 LDS-staged fused, 2 two-pass,
 //                     3 wave-local fused with one tile per workgroup, 4 as 3 with the
-//                     tile staged through LDS by coalesced 16-byte loads and stores
+//                     tile staged through LDS by coalesced 16-byte loads and stores,
+//                     5..12 as 3 (odd) or 4 (even) with at most 16, 10, 6, 4 resident
+//                     workgroups per CU
 //   128 x 128:        0 split fused (two wavefronts per transform), 1 LDS-staged fused, 2 two-pass,
 //                     3 split fused with the rows (inverse: columns) read through an LDS copy
 //                     of the array
@@ -1276,7 +1305,7 @@ int launch_fused(const DeviceTables* t, const Job& j)
 //   other, an axis of 256: 0 two-pass
 int fp32_variant_count(int rows, int cols, int)
 {
-    if (rows <= 64 && cols <= 64) return 5;
+    if (rows <= 64 && cols <= 64) return 13;
     if (rows == 128 && cols == 128) return 4;
     if (rows <= 128 && cols <= 128) return 2;
     if (rows == 256 && cols == 256) return 5;
@@ -1284,12 +1313,18 @@ int fp32_variant_count(int rows, int cols, int)
 }
 
 // Variant used until the tuner measures otherwise (fastest in measurements on MI355X
-// with 512 MiB batches): for axes <= 64 the staged wave-local kernel for round trips and
-// for axes <= 16, else the plain one (one tile per workgroup); the staged split kernel
-// for 128 x 128, the split kernel for 256 x 256.
+// with 512 MiB batches), by the longer axis of arrays up to 64 x 64: 8 staged; 16 staged
+// with at most 16 workgroups per CU; 32 at most 10 per CU, staged for the round trip;
+// 64 staged with at most 4 per CU (forward, inverse) or uncapped (round trip, whose
+// transforms need the wavefronts).  The staged split kernel for 128 x 128, the split
+// kernel for 256 x 256.
 int fp32_default_variant(int rows, int cols, int dir)
 {
-    if (rows <= 64 && cols <= 64) return dir == DCT2D_ROUNDTRIP || (rows <= 16 && cols <= 16) ? 4 : 3;
+    if (rows <= 64 && cols <= 64) {
+        const int m = rows > cols ? rows : cols;
+        const bool rt = dir == DCT2D_ROUNDTRIP;
+        return m <= 8 ? 4 : m <= 16 ? 6 : m <= 32 ? (rt ? 8 : 7) : (rt ? 4 : 12);
+    }
     if (rows == 128 && cols == 128) return 3;
     return 0;
 }
@@ -1297,7 +1332,7 @@ int fp32_default_variant(int rows, int cols, int dir)
 int launch_fp32(const DeviceTables* t, const Job& j)
 {
     if (j.rows <= 64 && j.cols <= 64) {
-        if (j.variant == 0 || j.variant == 3 || j.variant == 4) return launch_wave(t, j);
+        if (j.variant == 0 || j.variant >= 3) return launch_wave(t, j);
         if (j.variant == 1) return launch_fused(t, j);
         return launch_two_pass(t, j);
     }

@@ -211,8 +211,9 @@ def test_every_variant(h, w, direction):
 @pytest.mark.parametrize("direction", DIRS)
 def test_wave_variants_many_tiles(h, w, direction):
     """The wave-local variants (0: grid-stride over several tiles per workgroup, 4: tiles
-    staged through LDS with whole-tile 16-byte moves) on a 64 MiB batch plus a ragged tail;
-    about 500 sampled arrays (the first, the last and the tail among them) are checked."""
+    staged through LDS with whole-tile 16-byte moves, 7 and 12: plain and staged with the
+    resident workgroups per CU capped) on a 64 MiB batch plus a ragged tail; about 500
+    sampled arrays (the first, the last and the tail among them) are checked."""
     import torch
     dct = _lib()
     batch = (1 << 24) // (h * w) + 5
@@ -225,7 +226,7 @@ def test_wave_variants_many_tiles(h, w, direction):
     t = torch.from_numpy(x).cuda()
     out = torch.empty_like(t)
     try:
-        for v in (0, 4):
+        for v in (0, 4, 7, 12):
             dct.set_variant(h, w, direction, "fp32", v)
             out.fill_(float("nan"))
             dct.transform(t, out, direction, "fp32")
