@@ -156,3 +156,30 @@ def test_c4_full_ragged_sampled(direction):
     worst = _check(rg, out, direction, idx=sample, label="c4")
     print("c4 %s sampled %d items, worst e_rel %.3e" % (direction, sample.size, worst))
     plan.close()
+
+
+@pytest.mark.parametrize("direction", DIRS)
+def test_ragged_every_wave_variant(direction):
+    """Ragged plans reach the wave-local kernels through offset lists and the plan's base
+    slot; every variant of the 8..64 classes (grid-stride, staged, occupancy-capped) is
+    recorded and checked, including each class's partial last tile."""
+    import torch
+    dct = _lib()
+    mix = {8: 0.4, 16: 0.3, 32: 0.2, 64: 0.1}
+    rg = workloads.c4_ragged(blocks=1203, images=(), seed=24, mix=mix)  # 476, 350, 253, 124 blocks
+    sizes = sorted(mix)
+    keep = {n: dct.get_variant(n, n, direction, "fp32") for n in sizes}
+    nv = dct.variant_count(8, 8, direction, "fp32")
+    try:
+        for v in [0] + list(range(3, nv)):
+            for n in sizes:
+                dct.set_variant(n, n, direction, "fp32", v)
+            plan = dct.RaggedPlan(rg.offsets, rg.rows, rg.cols, direction, "fp32")
+            buf = torch.from_numpy(rg.data).cuda()
+            plan.execute(buf)
+            torch.cuda.synchronize()
+            _check(rg, buf.cpu().numpy(), direction, label="v%d" % v)
+            plan.close()
+    finally:
+        for n in sizes:
+            dct.set_variant(n, n, direction, "fp32", keep[n])
