@@ -248,8 +248,8 @@ def kernel_name(n, d, tuned):
             return "k_wave<%d, %d, %d, %s>" % (n, n, di, "true" if stage else "false")
         return "k_fused<%d, %d, %d>" % (n, n, di) if v == 1 else None
     if n == 128:
-        if v in (0, 3):
-            return "k_split128<%d, %s>" % (di, "true" if v == 3 else "false")
+        if v == 0 or v >= 3:
+            return "k_split128<%d, %s>" % (di, "true" if v in (3, 4) else "false")
         return "k_fused<128, 128, %d>" % di if v == 1 else None
     if n == 256:
         return None if v == 1 else "k_split256<%d>" % di

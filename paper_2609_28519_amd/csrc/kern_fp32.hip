@@ -1148,7 +1148,9 @@ int launch_split128_dir(const DeviceTables* t, const Job& j)
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_split128<DIR, STAGE>, 256, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
-    const int64_t cap = (int64_t)t->num_cu * per_cu * 4;
+    // variants 4, 5: one array per workgroup; 0, 3: a grid-stride loop over 4 x the
+    // resident workgroups
+    const int64_t cap = j.variant >= 4 ? ((int64_t)1 << 31) - 1 : (int64_t)t->num_cu * per_cu * 4;
     const unsigned grid = (unsigned)(j.batch < cap ? j.batch : cap);
     k_split128<DIR, STAGE><<<grid, 256, 0, j.stream>>>(j.addr(), j.batch, tw_for(t, 128));
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
@@ -1297,7 +1299,7 @@ int launch_fused(const DeviceTables* t, const Job& j)
 //                     workgroups per CU
 //   128 x 128:        0 split fused (two wavefronts per transform), 1 LDS-staged fused, 2 two-pass,
 //                     3 split fused with the rows (inverse: columns) read through an LDS copy
-//                     of the array
+//                     of the array, 4 and 5 as 3 and 0 with one array per workgroup
 //   other axes <=128: 0 LDS-staged fused, 1 two-pass
 //   256 x 256:        0 split fused (two groups of wavefronts, two LDS rounds), one
 //                     resident workgroup per CU; 1 two-pass; 2 split fused, one array
@@ -1306,7 +1308,7 @@ int launch_fused(const DeviceTables* t, const Job& j)
 int fp32_variant_count(int rows, int cols, int)
 {
     if (rows <= 64 && cols <= 64) return 13;
-    if (rows == 128 && cols == 128) return 4;
+    if (rows == 128 && cols == 128) return 6;
     if (rows <= 128 && cols <= 128) return 2;
     if (rows == 256 && cols == 256) return 5;
     return 1;
@@ -1316,8 +1318,8 @@ int fp32_variant_count(int rows, int cols, int)
 // with 512 MiB batches), by the longer axis of arrays up to 64 x 64: 8 staged; 16 staged
 // with at most 16 workgroups per CU; 32 at most 10 per CU, staged for the round trip;
 // 64 staged with at most 4 per CU (forward, inverse) or uncapped (round trip, whose
-// transforms need the wavefronts).  The staged split kernel for 128 x 128, the split
-// kernel for 256 x 256.
+// transforms need the wavefronts).  The staged split kernel for 128 x 128 with one array
+// per workgroup, the split kernel for 256 x 256.
 int fp32_default_variant(int rows, int cols, int dir)
 {
     if (rows <= 64 && cols <= 64) {
@@ -1325,7 +1327,7 @@ int fp32_default_variant(int rows, int cols, int dir)
         const bool rt = dir == DCT2D_ROUNDTRIP;
         return m <= 8 ? 4 : m <= 16 ? 6 : m <= 32 ? (rt ? 8 : 7) : (rt ? 4 : 12);
     }
-    if (rows == 128 && cols == 128) return 3;
+    if (rows == 128 && cols == 128) return 4;
     return 0;
 }
 
@@ -1337,7 +1339,7 @@ int launch_fp32(const DeviceTables* t, const Job& j)
         return launch_two_pass(t, j);
     }
     if (j.rows == 128 && j.cols == 128) {
-        if (j.variant == 0 || j.variant == 3) return launch_split128(t, j, j.variant == 3);
+        if (j.variant == 0 || j.variant >= 3) return launch_split128(t, j, j.variant == 3 || j.variant == 4);
         if (j.variant == 1) return launch_fused(t, j);
         return launch_two_pass(t, j);
     }
