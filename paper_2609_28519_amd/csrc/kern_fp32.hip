@@ -145,14 +145,14 @@ k_fused(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* 
     }
 }
 
-// Wave-local fused kernel (one wavefront per workgroup, rows and cols <= 64): each
-// lane loads its row straight from HBM into registers (the lanes of a wavefront cover
-// 64/TB consecutive arrays, so the wavefront reads one contiguous span), transforms
-// it, and writes it into a padded LDS tile; after a wavefront-local barrier each lane
-// reads one column, transforms it and stores it directly (consecutive lanes hold
-// consecutive columns).  The round trip goes back through LDS for the inverse row
-// pass and leaves with 16-byte row stores.  Only the row-to-column re-layout uses
-// LDS, and no barrier couples different wavefronts.
+// Wave-local fused kernel (one wavefront per workgroup, rows and cols <= 64; a tile is
+// the 64/TB consecutive arrays that the lanes of the wavefront cover): each lane
+// transforms one row and writes it into the LDS tile; after a wavefront-local barrier
+// each lane reads one column, transforms it and stores it (consecutive lanes hold
+// consecutive columns).  The round trip goes back through LDS for the inverse row pass.
+// Plain variant: the rows come straight from HBM into registers and the results leave
+// from registers.  Staged variant: the tile enters and leaves the LDS tile by whole-tile
+// coalesced 16-byte moves.  No barrier couples different wavefronts.
 template <int H, int W>
 struct WaveCfg {
     static constexpr int TB = cmax(H, W);
