@@ -243,6 +243,8 @@ def kernel_name(n, d, tuned):
     if path != "fp32":
         return None
     if n <= 64:
+        if n == 64 and v >= 13:
+            return "k_split64<%d>" % di
         if v == 0 or v >= 3:
             stage = v == 4 or (v >= 5 and (v - 5) % 2 == 1)
             return "k_wave<%d, %d, %d, %s>" % (n, n, di, "true" if stage else "false")

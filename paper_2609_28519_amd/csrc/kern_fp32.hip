@@ -516,6 +516,165 @@ k_split128(Addr a, int64_t batch, const float2* __restrict__ tw_in)
     }
 }
 
+// Split fused kernel for 64 x 64 arrays: one 128-thread workgroup (two wavefronts) per
+// array; every length-64 transform is shared by the two wavefronts through the top level
+// of the even/odd recursion (wavefront 0: the DCT-II_32 / DCT-III_32 half, wavefront 1:
+// the DCT-IV_32 half), so a lane holds 32 values and a CU holds twice the wavefronts of
+// the wave-local kernel in the same LDS.  The array lives in one unpadded, XOR-swizzled
+// 64 x 64 LDS tile (the layout of WaveCfg<64, 64>) and enters and leaves by whole-array
+// coalesced 16-byte moves.  Between the passes each row (column) is kept as two halves,
+// wavefront 0's results in physical columns (rows) 0..31 and wavefront 1's in 32..63.
+//   forward:    rows -> [even | odd coefficient] halves | columns -> [even ; odd]
+//               halves | out, each 16-byte chunk gathered from the permuted tile
+//   round trip: forward rows | forward and inverse columns in registers -> [p ; q]
+//               (z = p + q, z[63-n] = p - q) | inverse rows of the recombined columns
+//               -> [p | q] | out, recombining each chunk
+//   inverse:    inverse columns -> [p ; q], stored in the column order the forward rows
+//               leave | then as the round trip
+// One array, as seen by the wavefront of one role (each role runs its own straight-line
+// code; both pass the same barriers).
+template <int DIR, int ROLE>
+__device__ __forceinline__ void split64_array(const Addr& a, int64_t b, float* T, const float2* tw_in)
+{
+    using C = WaveCfg<64, 64>;
+    constexpr int N = 64, H = 32;
+    {
+        // lane indices are made opaque per array, so the LDS offsets derived from them are
+        // computed where they are used instead of being hoisted out of the loop and held
+        int t = threadIdx.x;
+        asm volatile("" : "+v"(t));
+        const int l = t & 63; // row or column of this lane
+        {
+            // in: chunk c = i * 128 + t is row c / 16, 16-byte group c % 16
+            const gfloat* src = a.src(b);
+            float4 q[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) q[i] = *reinterpret_cast<const gfloat4*>(src + 4 * (i * 128 + t));
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int c = i * 128 + t;
+                *reinterpret_cast<float4*>(T + C::at4(c >> 4, c & 15)) = q[i];
+            }
+        }
+        __syncthreads();
+        float v[H], y[H];
+        if (DIR != DCT2D_INVERSE) {
+            // ---- forward rows: row l; u[n] = x[n] + x[63-n] (role 0), w[n] = x[n] - x[63-n]
+            twptr tw = per_iteration(tw_in);
+            {
+                float x[N];
+                lds_row_in<N, N>(x, T, l);
+#pragma unroll
+                for (int n = 0; n < H; ++n) v[n] = ROLE == 0 ? x[n] + x[N - 1 - n] : x[n] - x[N - 1 - n];
+            }
+            if constexpr (ROLE == 0) dct2_rec<N, H>(v, y, tw); else dct4_scaled<N, H>(v, y, tw);
+            __syncthreads(); // every row is read before the halves overwrite it
+#pragma unroll
+            for (int g = 0; g < 8; ++g)
+                *reinterpret_cast<float4*>(T + C::at4(l, 8 * ROLE + g)) =
+                    make_float4(y[4 * g], y[4 * g + 1], y[4 * g + 2], y[4 * g + 3]);
+            __syncthreads();
+            // ---- columns: physical column l (logical column 2 l, or 2 (l - 32) + 1)
+            tw = per_iteration(tw_in);
+            {
+                float x[N];
+#pragma unroll
+                for (int r = 0; r < N; ++r) x[r] = T[C::at(r, l)];
+#pragma unroll
+                for (int n = 0; n < H; ++n) v[n] = ROLE == 0 ? x[n] + x[N - 1 - n] : x[n] - x[N - 1 - n];
+            }
+            if constexpr (ROLE == 0) dct2_rec<N, H>(v, y, tw); else dct4_scaled<N, H>(v, y, tw);
+            if (DIR == DCT2D_ROUNDTRIP) {
+                tw_fence(tw);
+                // p (role 0: DCT-III_32 of the even coefficients) or q (role 1: DCT-IV_32 of the odd)
+                if constexpr (ROLE == 0) dct3_rec<N, H>(y, v, tw); else dct4_scaled<N, H>(y, v, tw);
+            }
+            __syncthreads(); // every column is read before the halves overwrite it
+#pragma unroll
+            for (int n = 0; n < H; ++n) T[C::at(H * ROLE + n, l)] = DIR == DCT2D_ROUNDTRIP ? v[n] : y[n];
+            __syncthreads();
+        } else {
+            // ---- inverse columns: logical column l; role 0 inverts the even coefficient
+            // rows (DCT-III_32 -> p), role 1 the odd ones (DCT-IV_32 -> q).  The halves go
+            // to physical column l / 2 (l even) or 32 + l / 2, the column order that the
+            // forward rows leave, so the inverse rows below serve both directions.
+            twptr tw = per_iteration(tw_in);
+#pragma unroll
+            for (int k = 0; k < H; ++k) v[k] = T[C::at(2 * k + ROLE, l)];
+            if constexpr (ROLE == 0) dct3_rec<N, H>(v, y, tw); else dct4_scaled<N, H>(v, y, tw);
+            __syncthreads(); // every column is read before the halves overwrite it
+            const int pc = (l & 1) * H + (l >> 1);
+#pragma unroll
+            for (int n = 0; n < H; ++n) T[C::at(H * ROLE + n, pc)] = y[n];
+            __syncthreads();
+        }
+        if (DIR != DCT2D_FORWARD) {
+            // ---- inverse rows: row l.  The tile holds the columns as [p ; q] halves,
+            // logical column 2 k + s at physical column 32 s + k, Z[r][.] = p[r] + q[r] for
+            // r < 32 and p[63-r] - q[63-r] above.  Role 0 inverts the even coefficients
+            // (DCT-III_32 -> p), role 1 the odd ones (DCT-IV_32 -> q).
+            twptr tw = per_iteration(tw_in);
+            {
+                const int rr = l < H ? l : N - 1 - l;
+                const float sg = l < H ? 1.f : -1.f; // exact: one rounding, as p +- q
+#pragma unroll
+                for (int g = 0; g < 8; ++g) {
+                    const float4 p4 = *reinterpret_cast<const float4*>(T + C::at4(rr, 8 * ROLE + g));
+                    const float4 q4 = *reinterpret_cast<const float4*>(T + C::at4(H + rr, 8 * ROLE + g));
+                    v[4 * g] = __builtin_fmaf(sg, q4.x, p4.x);
+                    v[4 * g + 1] = __builtin_fmaf(sg, q4.y, p4.y);
+                    v[4 * g + 2] = __builtin_fmaf(sg, q4.z, p4.z);
+                    v[4 * g + 3] = __builtin_fmaf(sg, q4.w, p4.w);
+                }
+            }
+            if constexpr (ROLE == 0) dct3_rec<N, H>(v, y, tw); else dct4_scaled<N, H>(v, y, tw);
+            __syncthreads(); // every row is read before the halves overwrite it
+#pragma unroll
+            for (int g = 0; g < 8; ++g)
+                *reinterpret_cast<float4*>(T + C::at4(l, 8 * ROLE + g)) =
+                    make_float4(y[4 * g], y[4 * g + 1], y[4 * g + 2], y[4 * g + 3]);
+            __syncthreads();
+        }
+        {
+            // out: chunk c = i * 128 + t is output row R = c / 16, columns 4 g .. 4 g + 3
+            gfloat* dst = a.dst(b);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int c = i * 128 + t, R = c >> 4, g = c & 15;
+                float4 o;
+                if (DIR == DCT2D_FORWARD) {
+                    // logical (R, 4 g + j) sits at physical row (R odd) 32 + R / 2, column
+                    // (j odd) 32 + 2 g + j / 2
+                    const int pr = (R & 1) * H + (R >> 1);
+                    o = make_float4(T[C::at(pr, 2 * g)], T[C::at(pr, H + 2 * g)], T[C::at(pr, 2 * g + 1)],
+                                    T[C::at(pr, H + 2 * g + 1)]);
+                } else {
+                    // row R as [p | q]: x[m] = p[m] + q[m], x[63-m] = p[m] - q[m]
+                    const int gg = g < 8 ? g : 15 - g;
+                    const float4 p4 = *reinterpret_cast<const float4*>(T + C::at4(R, gg));
+                    const float4 q4 = *reinterpret_cast<const float4*>(T + C::at4(R, 8 + gg));
+                    o = g < 8 ? make_float4(p4.x + q4.x, p4.y + q4.y, p4.z + q4.z, p4.w + q4.w)
+                              : make_float4(p4.w - q4.w, p4.z - q4.z, p4.y - q4.y, p4.x - q4.x);
+                }
+                *reinterpret_cast<gfloat4*>(dst + 4 * c) = o;
+            }
+        }
+        __syncthreads(); // the tile is read out before the next array is staged in
+    }
+}
+
+template <int DIR>
+__global__ void __launch_bounds__(128, 4) // four wavefronts per SIMD: at most 128 VGPRs
+k_split64(Addr a, int64_t batch, const float2* __restrict__ tw_in)
+{
+    __shared__ float4 T4[64 * 64 / 4];
+    float* const T = reinterpret_cast<float*>(T4);
+    const bool odd = threadIdx.x >= 64; // the role (uniform per wavefront)
+    for (int64_t b = blockIdx.x; b < batch; b += gridDim.x) {
+        if (odd) split64_array<DIR, 1>(a, b, T, tw_in); else split64_array<DIR, 0>(a, b, T, tw_in);
+    }
+}
+
 // Fused kernel for 256 x 256 arrays: one 512-thread workgroup per array, one workgroup
 // per CU.  Every length-256 transform is shared by two halves of the workgroup through
 // the top level of the even/odd recursion (dct1d.hpp), so each thread holds 128 values:
@@ -1170,6 +1329,28 @@ int launch_split128(const DeviceTables* t, const Job& j, bool stage)
 }
 
 template <int DIR>
+int launch_split64_dir(const DeviceTables* t, const Job& j)
+{
+    // one array per workgroup; variants 14, 15 cap the resident workgroups per CU at 6, 4
+    // (an LDS reservation, as for the wave-local kernels)
+    const unsigned grid = (unsigned)(j.batch < (((int64_t)1 << 31) - 1) ? j.batch : (((int64_t)1 << 31) - 1));
+    const size_t tile = 64 * 64 * sizeof(float);
+    const size_t per_wg = j.variant >= 14 ? (size_t)(160 * 1024 / (j.variant == 14 ? 6 : 4)) & ~(size_t)255 : tile;
+    const size_t reserve = per_wg > tile ? per_wg - tile : 0;
+    k_split64<DIR><<<grid, 128, reserve, j.stream>>>(j.addr(), j.batch, tw_for(t, 64));
+    return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
+}
+
+int launch_split64(const DeviceTables* t, const Job& j)
+{
+    switch (j.dir) {
+    case DCT2D_FORWARD: return launch_split64_dir<DCT2D_FORWARD>(t, j);
+    case DCT2D_INVERSE: return launch_split64_dir<DCT2D_INVERSE>(t, j);
+    default: return launch_split64_dir<DCT2D_ROUNDTRIP>(t, j);
+    }
+}
+
+template <int DIR>
 int launch_split256_dir(const DeviceTables* t, const Job& j)
 {
     int per_cu = 0;
@@ -1296,7 +1477,9 @@ int launch_fused(const DeviceTables* t, const Job& j)
 //                     3 wave-local fused with one tile per workgroup, 4 as 3 with the
 //                     tile staged through LDS by coalesced 16-byte loads and stores,
 //                     5..12 as 3 (odd) or 4 (even) with at most 16, 10, 6, 4 resident
-//                     workgroups per CU
+//                     workgroups per CU; 64 x 64 only: 13 split fused (two wavefronts per
+//                     transform, one array per workgroup), 14, 15 as 13 with at most 6, 4
+//                     resident workgroups per CU
 //   128 x 128:        0 split fused (two wavefronts per transform), 1 LDS-staged fused, 2 two-pass,
 //                     3 split fused with the rows (inverse: columns) read through an LDS copy
 //                     of the array, 4 and 5 as 3 and 0 with one array per workgroup
@@ -1307,6 +1490,7 @@ int launch_fused(const DeviceTables* t, const Job& j)
 //   other, an axis of 256: 0 two-pass
 int fp32_variant_count(int rows, int cols, int)
 {
+    if (rows == 64 && cols == 64) return 16;
     if (rows <= 64 && cols <= 64) return 13;
     if (rows == 128 && cols == 128) return 6;
     if (rows <= 128 && cols <= 128) return 2;
@@ -1317,14 +1501,16 @@ int fp32_variant_count(int rows, int cols, int)
 // Variant used until the tuner measures otherwise (fastest in measurements on MI355X
 // with 512 MiB batches), by the longer axis of arrays up to 64 x 64: 8 staged; 16 staged
 // with at most 16 workgroups per CU; 32 at most 10 per CU, staged for the round trip;
-// 64 staged with at most 4 per CU (forward, inverse) or uncapped (round trip, whose
-// transforms need the wavefronts).  The staged split kernel for 128 x 128 with one array
-// per workgroup, the split kernel for 256 x 256.
+// 64 x 64 the two-wavefront split kernel, with at most 4 workgroups per CU for forward and
+// inverse (other shapes with a 64 axis: staged, at most 4 per CU, uncapped for the round
+// trip).  The staged split kernel for 128 x 128 with one array per workgroup, the split
+// kernel for 256 x 256.
 int fp32_default_variant(int rows, int cols, int dir)
 {
     if (rows <= 64 && cols <= 64) {
         const int m = rows > cols ? rows : cols;
         const bool rt = dir == DCT2D_ROUNDTRIP;
+        if (rows == 64 && cols == 64) return rt ? 13 : 15;
         return m <= 8 ? 4 : m <= 16 ? 6 : m <= 32 ? (rt ? 8 : 7) : (rt ? 4 : 12);
     }
     if (rows == 128 && cols == 128) return 4;
@@ -1334,6 +1520,7 @@ int fp32_default_variant(int rows, int cols, int dir)
 int launch_fp32(const DeviceTables* t, const Job& j)
 {
     if (j.rows <= 64 && j.cols <= 64) {
+        if (j.variant >= 13) return launch_split64(t, j);
         if (j.variant == 0 || j.variant >= 3) return launch_wave(t, j);
         if (j.variant == 1) return launch_fused(t, j);
         return launch_two_pass(t, j);

@@ -212,8 +212,9 @@ def test_every_variant(h, w, direction):
 def test_wave_variants_many_tiles(h, w, direction):
     """The wave-local variants (0: grid-stride over several tiles per workgroup, 4: tiles
     staged through LDS with whole-tile 16-byte moves, 7 and 12: plain and staged with the
-    resident workgroups per CU capped) on a 64 MiB batch plus a ragged tail; about 500
-    sampled arrays (the first, the last and the tail among them) are checked."""
+    resident workgroups per CU capped) and, at 64 x 64, the two-wavefront split kernel (13)
+    on a 64 MiB batch plus a ragged tail; about 500 sampled arrays (the first, the last and
+    the tail among them) are checked."""
     import torch
     dct = _lib()
     batch = (1 << 24) // (h * w) + 5
@@ -226,7 +227,7 @@ def test_wave_variants_many_tiles(h, w, direction):
     t = torch.from_numpy(x).cuda()
     out = torch.empty_like(t)
     try:
-        for v in (0, 4, 7, 12):
+        for v in (0, 4, 7, 12) + ((13, 15) if h == w == 64 else ()):
             dct.set_variant(h, w, direction, "fp32", v)
             out.fill_(float("nan"))
             dct.transform(t, out, direction, "fp32")
