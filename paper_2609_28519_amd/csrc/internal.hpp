@@ -23,6 +23,11 @@ struct DeviceTables {
     uint16_t* q_bf16[kNumDense] = {};   // 3 planes: hi, mid, lo (bf16 bit patterns)
     uint16_t* q_f16[kNumDense] = {};    // 2 planes: hi, lo (fp16 bit patterns)
     uint8_t* q_f8[kNumDense] = {};      // 1 plane: fp8 e4m3 of Q * 2^kF8QShift
+    // the same three split tables of Q^T (row-major), so that products with Q read their
+    // operand columns as contiguous runs too
+    uint16_t* q_bf16_t[kNumDense] = {};
+    uint16_t* q_f16_t[kNumDense] = {};
+    uint8_t* q_f8_t[kNumDense] = {};
     // Dense Q_n for arbitrary image axes (n <= 1024), generated on demand at plan time.
     void* pool = nullptr;               // single allocation holding everything above
     size_t pool_bytes = 0;

@@ -102,6 +102,9 @@ struct QTab {
     const uint16_t* hf; // 2 planes
     const uint8_t* f8;  // 1 plane (Q * 2^kF8QShift)
     int n;
+    const uint16_t* bft; // the same planes of Q^T
+    const uint16_t* hft;
+    const uint8_t* f8t;
 };
 
 __device__ __forceinline__ float bf16_bits_to_f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
@@ -620,7 +623,9 @@ k_mfma32(Addr a, int64_t batch, QTab q)
 // accumulator of tile (K, I) after pass 1 serves as the A operand of tile (I, K) in pass 2
 // (the same transpose-by-reuse as the 32 x 32 kernel, applied tile-wise).
 // B tile (K, J) of Q^T (forward) or Q (inverse), split part p, in the lane's slots:
-// bt[p][s][j] = B[32 K + k(s, j)][32 J + c].  Read from the (cache-resident) tables at use.
+// bt[p][s][j] = B[32 K + k(s, j)][32 J + c].  Read from the (cache-resident) tables at use:
+// B[k][n] is entry (n, k) of Q (forward) or of Q^T (inverse), so a lane's slots are runs
+// of four consecutive entries in either direction.
 template <int MODE>
 __device__ __forceinline__ void load_b64_tile(float (&bt)[3][2][8], const QTab& q, bool inv, int h, int c, int K,
                                               int J)
@@ -635,9 +640,9 @@ __device__ __forceinline__ void load_b64_tile(float (&bt)[3][2][8], const QTab& 
                 const int n = 32 * J + c;
                 float v = 0.f;
                 if (p < ModeInfo<MODE>::parts) {
-                    const int r = inv ? k : n, cc = inv ? n : k; // B = Q (inverse) or Q^T
-                    const int i = r * 64 + cc;
-                    v = ModeInfo<MODE>::f16 ? f16_bits_to_f(q.hf[p * 4096 + i]) : bf16_bits_to_f(q.bf[p * 4096 + i]);
+                    const int i = n * 64 + k;
+                    v = ModeInfo<MODE>::f16 ? f16_bits_to_f((inv ? q.hft : q.hf)[p * 4096 + i])
+                                            : bf16_bits_to_f((inv ? q.bft : q.bf)[p * 4096 + i]);
                 }
                 bt[p][s][j] = v;
             }
@@ -651,7 +656,7 @@ __device__ __forceinline__ long load_b64_f8(const QTab& q, bool inv, int h, int 
     for (int j = 0; j < 8; ++j) {
         const int k = 32 * K + 8 * (2 * s + j / 4) + 4 * h + (j & 3);
         const int n = 32 * J + c;
-        const uint8_t byte = inv ? q.f8[k * 64 + n] : q.f8[n * 64 + k];
+        const uint8_t byte = (inv ? q.f8t : q.f8)[n * 64 + k];
         v |= (uint64_t)byte << (8 * j);
     }
     return (long)v;
@@ -813,7 +818,7 @@ QTab qtab(const DeviceTables* t, int n)
 {
     int i = 0;
     while ((8 << i) < n) ++i;
-    return QTab{t->q_bf16[i], t->q_f16[i], t->q_f8[i], n};
+    return QTab{t->q_bf16[i], t->q_f16[i], t->q_f8[i], n, t->q_bf16_t[i], t->q_f16_t[i], t->q_f8_t[i]};
 }
 
 template <int N, int MODE, int DIR, int UNROLL>

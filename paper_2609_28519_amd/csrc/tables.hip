@@ -116,13 +116,14 @@ __device__ double q_entry(int n, int k, int j)
     return a * cos_half_turn((long long)(2 * j + 1) * k, n);
 }
 
-__global__ void k_dense(int n, float* qf, uint16_t* qb, uint16_t* qh, uint8_t* q8)
+// Entry i of Q_n (transposed: of Q_n^T) and its splits; qf may be null.
+__global__ void k_dense(int n, bool transposed, float* qf, uint16_t* qb, uint16_t* qh, uint8_t* q8)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int nn = n * n;
     if (i >= nn) return;
-    const double q = q_entry(n, i / n, i % n);
-    qf[i] = (float)q;
+    const double q = transposed ? q_entry(n, i % n, i / n) : q_entry(n, i / n, i % n);
+    if (qf) qf[i] = (float)q;
     // bf16: 8 significant bits, min quantum 2^-133
     const double b0 = round_sig(q, 8, -133);
     const double b1 = round_sig(q - b0, 8, -133);
@@ -182,13 +183,15 @@ int tables_init_device(int device)
     }
     const size_t tw_bytes = align_up(tw_entries * sizeof(float2), 256);
     off += tw_bytes;
-    size_t dense_off[kNumDense][4];
+    size_t dense_off[kNumDense][7];
     for (int i = 0; i < kNumDense; ++i) {
         const size_t nn = (size_t)(8 << i) * (8 << i);
         dense_off[i][0] = off; off = align_up(off + nn * 4, 256);
-        dense_off[i][1] = off; off = align_up(off + 3 * nn * 2, 256);
-        dense_off[i][2] = off; off = align_up(off + 2 * nn * 2, 256);
-        dense_off[i][3] = off; off = align_up(off + nn, 256);
+        for (int tr = 0; tr < 2; ++tr) { // Q, then Q^T
+            dense_off[i][1 + 3 * tr] = off; off = align_up(off + 3 * nn * 2, 256);
+            dense_off[i][2 + 3 * tr] = off; off = align_up(off + 2 * nn * 2, 256);
+            dense_off[i][3 + 3 * tr] = off; off = align_up(off + nn, 256);
+        }
     }
     void* pool = nullptr;
     if (hipMalloc(&pool, off) != hipSuccess) {
@@ -211,7 +214,11 @@ int tables_init_device(int device)
         t->q_bf16[i] = reinterpret_cast<uint16_t*>(base + dense_off[i][1]);
         t->q_f16[i] = reinterpret_cast<uint16_t*>(base + dense_off[i][2]);
         t->q_f8[i] = reinterpret_cast<uint8_t*>(base + dense_off[i][3]);
-        k_dense<<<(n * n + 255) / 256, 256>>>(n, t->q_f32[i], t->q_bf16[i], t->q_f16[i], t->q_f8[i]);
+        t->q_bf16_t[i] = reinterpret_cast<uint16_t*>(base + dense_off[i][4]);
+        t->q_f16_t[i] = reinterpret_cast<uint16_t*>(base + dense_off[i][5]);
+        t->q_f8_t[i] = reinterpret_cast<uint8_t*>(base + dense_off[i][6]);
+        k_dense<<<(n * n + 255) / 256, 256>>>(n, false, t->q_f32[i], t->q_bf16[i], t->q_f16[i], t->q_f8[i]);
+        k_dense<<<(n * n + 255) / 256, 256>>>(n, true, nullptr, t->q_bf16_t[i], t->q_f16_t[i], t->q_f8_t[i]);
     }
     const hipError_t e1 = hipGetLastError();
     const hipError_t e2 = hipDeviceSynchronize();
