@@ -238,4 +238,3 @@ def test_wave_variants_many_tiles(h, w, direction):
                 h, w, v, direction, e.max())
     finally:
         dct.set_variant(h, w, direction, "fp32", keep)
-
