@@ -7,11 +7,13 @@
 //   column pass   Y = Q_h X      (forward)    Y = Q_h^T X   (inverse)
 //   row pass      Y = X Q_w^T    (forward)    Y = X Q_w     (inverse)
 //
-// Tiled product: a 256-thread workgroup computes a 64 x 64 output tile, each thread a
-// 4 x 4 micro-tile, over K in chunks of 16 staged in LDS.  The 16 products of a chunk
-// are summed in a fresh partial that is then added to the running sum (blocked
-// summation), which keeps the float32 accumulation error near 4 unit roundoffs per
-// pass at L = 1024 instead of growing like sqrt(L/6).
+// Tiled product: a 256-thread workgroup computes a 64 x 64 output tile over K in chunks
+// of 16 staged in LDS.  The 16 products of a chunk are summed in a fresh partial that is
+// then added to the running sum (blocked summation), which keeps the float32
+// accumulation error near 4 unit roundoffs per pass at L = 1024 instead of growing like
+// sqrt(L/6).  The even/odd form (axes divisible by 8: every image axis of the workloads)
+// runs the products on the matrix cores in float32; the plain form, for other axes,
+// gives each thread a 4 x 4 micro-tile on the vector ALU.
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
@@ -20,6 +22,7 @@ namespace dct {
 namespace {
 
 constexpr int BM = 64, BN = 64, BK = 16;
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // Generic strided operand: element (i, k) at p[i * si + k * sk].
 struct Mat {
@@ -99,11 +102,127 @@ k_dense_pass(Addr a, bool img_is_a, Mat qm, int64_t img_si, int64_t img_sk, int 
 //            x[n] = a[n] + b[n],  x[L-1-n] = a[n] - b[n]
 // i.e. two products of half the depth (half the flops of the dense pass), with the
 // butterflies fused into the operand loads (forward) or the stores (inverse).  A
-// workgroup computes the 64 x 64 tiles of both products for the same output positions,
-// each thread a 4 x 4 micro-tile of each, over K in chunks of 16 with blocked summation.
+// workgroup computes the 64 x 64 tiles of both products for the same output positions
+// on the matrix cores in float32 (each wavefront a 32 x 32 sub-tile of each), over K in
+// chunks of 16 with blocked summation.
 // ROW: transform along the rows (length L = cols); else along the columns (L = rows).
 // The source and destination never overlap (the ragged planner ping-pongs through its
 // workspace).
+// One chunk's operands as loaded from HBM, before the butterflies: u, v from the image,
+// b1, b2 from Q_L (zeros outside the matrices).
+struct EoRegs {
+    float4 u, v, b1, b2;
+};
+
+template <bool ROW, bool INV>
+__device__ __forceinline__ EoRegs eo_fetch(const gfloat* x, const gfloat* q, int rows, int cols, int L, int i0,
+                                           int j0, int k0, int t)
+{
+    const int HL = L / 2;
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    EoRegs r{z, z, z, z};
+    if (ROW) {
+        // image rows i0 + t / 4, depth k0 + 4 (t % 4) .. +3
+        const int gi = i0 + t / 4, gk = k0 + 4 * (t % 4);
+        if (gi < rows && gk < HL) {
+            const gfloat* xr = x + (int64_t)gi * cols;
+            if (!INV) {
+                r.u = *reinterpret_cast<const gfloat4*>(xr + gk);          // x[gk .. gk+3]
+                r.v = *reinterpret_cast<const gfloat4*>(xr + L - 4 - gk);  // x[L-1-gk-3 .. L-1-gk]
+            } else {
+                r.u = *reinterpret_cast<const gfloat4*>(xr + 2 * gk);      // Y[2gk .. 2gk+3]
+                r.v = *reinterpret_cast<const gfloat4*>(xr + 2 * gk + 4);  // Y[2gk+4 .. 2gk+7]
+            }
+        }
+        if (!INV) {
+            const int gh = j0 + t / 4, gk2 = k0 + 4 * (t % 4);
+            if (gh < HL && gk2 < HL) {
+                r.b1 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gh) * L + gk2);
+                r.b2 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gh + 1) * L + gk2);
+            }
+        } else {
+            const int gk2 = k0 + t / 16, gh = j0 + 4 * (t % 16);
+            if (gk2 < HL && gh < HL) {
+                r.b1 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gk2) * L + gh);
+                r.b2 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gk2 + 1) * L + gh);
+            }
+        }
+    } else {
+        if (!INV) {
+            const int gh = i0 + t / 4, gk = k0 + 4 * (t % 4);
+            if (gh < HL && gk < HL) {
+                r.b1 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gh) * L + gk);
+                r.b2 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gh + 1) * L + gk);
+            }
+        } else {
+            const int gk = k0 + t / 16, gh = i0 + 4 * (t % 16);
+            if (gk < HL && gh < HL) {
+                r.b1 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gk) * L + gh);
+                r.b2 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gk + 1) * L + gh);
+            }
+        }
+        // image depth rows k0 + t / 16, columns j0 + 4 (t % 16) .. +3
+        const int gk = k0 + t / 16, gj = j0 + 4 * (t % 16);
+        if (gk < HL && gj < cols) {
+            if (!INV) {
+                r.u = *reinterpret_cast<const gfloat4*>(x + (int64_t)gk * cols + gj);
+                r.v = *reinterpret_cast<const gfloat4*>(x + (int64_t)(L - 1 - gk) * cols + gj);
+            } else {
+                r.u = *reinterpret_cast<const gfloat4*>(x + (int64_t)(2 * gk) * cols + gj);
+                r.v = *reinterpret_cast<const gfloat4*>(x + (int64_t)(2 * gk + 1) * cols + gj);
+            }
+        }
+    }
+    return r;
+}
+
+// The butterflies (forward) or the even/odd split (inverse) of the fetched chunk, into the
+// LDS operand tiles: A (BM x BK, k-major), B (BK x BN).
+template <bool ROW, bool INV>
+__device__ __forceinline__ void eo_stage(const EoRegs& r, float (*A1)[BM + 4], float (*A2)[BM + 4],
+                                         float (*B1)[BN + 4], float (*B2)[BN + 4], int t)
+{
+    float4 p1, p2;
+    if (ROW) {
+        if (!INV) {
+            p1 = make_float4(r.u.x + r.v.w, r.u.y + r.v.z, r.u.z + r.v.y, r.u.w + r.v.x);
+            p2 = make_float4(r.u.x - r.v.w, r.u.y - r.v.z, r.u.z - r.v.y, r.u.w - r.v.x);
+        } else {
+            p1 = make_float4(r.u.x, r.u.z, r.v.x, r.v.z);
+            p2 = make_float4(r.u.y, r.u.w, r.v.y, r.v.w);
+        }
+        const int row = t / 4, c = 4 * (t % 4);
+        A1[c][row] = p1.x; A1[c + 1][row] = p1.y; A1[c + 2][row] = p1.z; A1[c + 3][row] = p1.w;
+        A2[c][row] = p2.x; A2[c + 1][row] = p2.y; A2[c + 2][row] = p2.z; A2[c + 3][row] = p2.w;
+        if (!INV) {
+            const int h = t / 4;
+            B1[c][h] = r.b1.x; B1[c + 1][h] = r.b1.y; B1[c + 2][h] = r.b1.z; B1[c + 3][h] = r.b1.w;
+            B2[c][h] = r.b2.x; B2[c + 1][h] = r.b2.y; B2[c + 2][h] = r.b2.z; B2[c + 3][h] = r.b2.w;
+        } else {
+            const int k = t / 16, cc = 4 * (t % 16);
+            *reinterpret_cast<float4*>(&B1[k][cc]) = r.b1;
+            *reinterpret_cast<float4*>(&B2[k][cc]) = r.b2;
+        }
+    } else {
+        if (!INV) {
+            const int h = t / 4, c = 4 * (t % 4);
+            A1[c][h] = r.b1.x; A1[c + 1][h] = r.b1.y; A1[c + 2][h] = r.b1.z; A1[c + 3][h] = r.b1.w;
+            A2[c][h] = r.b2.x; A2[c + 1][h] = r.b2.y; A2[c + 2][h] = r.b2.z; A2[c + 3][h] = r.b2.w;
+            p1 = make_float4(r.u.x + r.v.x, r.u.y + r.v.y, r.u.z + r.v.z, r.u.w + r.v.w);
+            p2 = make_float4(r.u.x - r.v.x, r.u.y - r.v.y, r.u.z - r.v.z, r.u.w - r.v.w);
+        } else {
+            const int k = t / 16, c = 4 * (t % 16);
+            *reinterpret_cast<float4*>(&A1[k][c]) = r.b1;
+            *reinterpret_cast<float4*>(&A2[k][c]) = r.b2;
+            p1 = r.u;
+            p2 = r.v;
+        }
+        const int k = t / 16, c = 4 * (t % 16);
+        *reinterpret_cast<float4*>(&B1[k][c]) = p1;
+        *reinterpret_cast<float4*>(&B2[k][c]) = p2;
+    }
+}
+
 template <bool ROW, bool INV>
 __global__ void __launch_bounds__(256)
 k_dense_eo(Addr a, const float* __restrict__ q_in, int rows, int cols)
@@ -122,136 +241,56 @@ k_dense_eo(Addr a, const float* __restrict__ q_in, int rows, int cols)
     // pass: (half index h, image column j)
     const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
     const int M = ROW ? rows : HL, N = ROW ? HL : cols;
-    const int ti = (t / 16) * 4, tj = (t % 16) * 4;
-    float acc1[4][4] = {}, acc2[4][4] = {};
+    const int lane = t & 63, wi = (t >> 6) >> 1, wj = (t >> 6) & 1;
+    f32x16 acc1, acc2;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { acc1[r] = 0.f; acc2[r] = 0.f; }
+    // software pipeline: the next chunk is fetched into registers while this one is
+    // multiplied
+    EoRegs nx = eo_fetch<ROW, INV>(x, q, rows, cols, L, i0, j0, 0, t);
     for (int k0 = 0; k0 < HL; k0 += BK) {
-        // ---- operand tiles: A (BM x BK, stored k-major), B (BK x BN) -------------------
-        if (ROW) {
-            // A from the image: rows i0 + r, depth k0 + 4 c4 .. +3 (r = t / 4, c4 = t % 4)
-            const int r = t / 4, c4 = t % 4, gi = i0 + r, gk = k0 + 4 * c4;
-            float4 p1 = make_float4(0.f, 0.f, 0.f, 0.f), p2 = p1;
-            if (gi < rows && gk < HL) {
-                const gfloat* xr = x + (int64_t)gi * cols;
-                if (!INV) {
-                    const float4 lo = *reinterpret_cast<const gfloat4*>(xr + gk);
-                    const float4 hi = *reinterpret_cast<const gfloat4*>(xr + L - 4 - gk); // x[L-1-gk-3 .. L-1-gk]
-                    p1 = make_float4(lo.x + hi.w, lo.y + hi.z, lo.z + hi.y, lo.w + hi.x);
-                    p2 = make_float4(lo.x - hi.w, lo.y - hi.z, lo.z - hi.y, lo.w - hi.x);
-                } else {
-                    const float4 e0 = *reinterpret_cast<const gfloat4*>(xr + 2 * gk);     // Y[2gk .. 2gk+3]
-                    const float4 e1 = *reinterpret_cast<const gfloat4*>(xr + 2 * gk + 4); // Y[2gk+4 .. 2gk+7]
-                    p1 = make_float4(e0.x, e0.z, e1.x, e1.z);
-                    p2 = make_float4(e0.y, e0.w, e1.y, e1.w);
-                }
-            }
-            A1[4 * c4][r] = p1.x; A1[4 * c4 + 1][r] = p1.y; A1[4 * c4 + 2][r] = p1.z; A1[4 * c4 + 3][r] = p1.w;
-            A2[4 * c4][r] = p2.x; A2[4 * c4 + 1][r] = p2.y; A2[4 * c4 + 2][r] = p2.z; A2[4 * c4 + 3][r] = p2.w;
-            // B from Q_L: B1(k, h) = Q[2h][k] (forward) or Q[2k][h] (inverse); B2 with 2h+1 / 2k+1
-            if (!INV) {
-                const int h = t / 4, c = 4 * (t % 4), gh = j0 + h, gk2 = k0 + c;
-                float4 b1 = make_float4(0.f, 0.f, 0.f, 0.f), b2 = b1;
-                if (gh < HL && gk2 < HL) {
-                    b1 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gh) * L + gk2);
-                    b2 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gh + 1) * L + gk2);
-                }
-                B1[c][h] = b1.x; B1[c + 1][h] = b1.y; B1[c + 2][h] = b1.z; B1[c + 3][h] = b1.w;
-                B2[c][h] = b2.x; B2[c + 1][h] = b2.y; B2[c + 2][h] = b2.z; B2[c + 3][h] = b2.w;
-            } else {
-                const int k = t / 16, c = 4 * (t % 16), gk2 = k0 + k, gh = j0 + c;
-                float4 b1 = make_float4(0.f, 0.f, 0.f, 0.f), b2 = b1;
-                if (gk2 < HL && gh < HL) {
-                    b1 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gk2) * L + gh);
-                    b2 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gk2 + 1) * L + gh);
-                }
-                *reinterpret_cast<float4*>(&B1[k][c]) = b1;
-                *reinterpret_cast<float4*>(&B2[k][c]) = b2;
-            }
-        } else {
-            // A from Q_L: A1(h, k) = Q[2h][k] (forward) or Q[2k][h] (inverse); A2 with 2h+1 / 2k+1
-            if (!INV) {
-                const int h = t / 4, c = 4 * (t % 4), gh = i0 + h, gk = k0 + c;
-                float4 a1 = make_float4(0.f, 0.f, 0.f, 0.f), a2 = a1;
-                if (gh < HL && gk < HL) {
-                    a1 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gh) * L + gk);
-                    a2 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gh + 1) * L + gk);
-                }
-                A1[c][h] = a1.x; A1[c + 1][h] = a1.y; A1[c + 2][h] = a1.z; A1[c + 3][h] = a1.w;
-                A2[c][h] = a2.x; A2[c + 1][h] = a2.y; A2[c + 2][h] = a2.z; A2[c + 3][h] = a2.w;
-            } else {
-                const int k = t / 16, c = 4 * (t % 16), gk = k0 + k, gh = i0 + c;
-                float4 a1 = make_float4(0.f, 0.f, 0.f, 0.f), a2 = a1;
-                if (gk < HL && gh < HL) {
-                    a1 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gk) * L + gh);
-                    a2 = *reinterpret_cast<const gfloat4*>(q + (int64_t)(2 * gk + 1) * L + gh);
-                }
-                *reinterpret_cast<float4*>(&A1[k][c]) = a1;
-                *reinterpret_cast<float4*>(&A2[k][c]) = a2;
-            }
-            // B from the image: depth rows k0 + k (k = t / 16), columns j0 + 4 (t % 16) .. +3
-            const int k = t / 16, c = 4 * (t % 16), gk = k0 + k, gj = j0 + c;
-            float4 p1 = make_float4(0.f, 0.f, 0.f, 0.f), p2 = p1;
-            if (gk < HL && gj < cols) {
-                if (!INV) {
-                    const float4 lo = *reinterpret_cast<const gfloat4*>(x + (int64_t)gk * cols + gj);
-                    const float4 hi = *reinterpret_cast<const gfloat4*>(x + (int64_t)(L - 1 - gk) * cols + gj);
-                    p1 = make_float4(lo.x + hi.x, lo.y + hi.y, lo.z + hi.z, lo.w + hi.w);
-                    p2 = make_float4(lo.x - hi.x, lo.y - hi.y, lo.z - hi.z, lo.w - hi.w);
-                } else {
-                    p1 = *reinterpret_cast<const gfloat4*>(x + (int64_t)(2 * gk) * cols + gj);
-                    p2 = *reinterpret_cast<const gfloat4*>(x + (int64_t)(2 * gk + 1) * cols + gj);
-                }
-            }
-            *reinterpret_cast<float4*>(&B1[k][c]) = p1;
-            *reinterpret_cast<float4*>(&B2[k][c]) = p2;
-        }
+        eo_stage<ROW, INV>(nx, A1, A2, B1, B2, t);
+        if (k0 + BK < HL) nx = eo_fetch<ROW, INV>(x, q, rows, cols, L, i0, j0, k0 + BK, t);
         __syncthreads();
-        float part1[4][4] = {}, part2[4][4] = {};
+        // ---- the chunk's 16 products of both halves on the matrix cores: wavefront w takes
+        // the 32 x 32 sub-tile (w / 2, w % 2); v_mfma_f32_32x32x2f32 takes A[i][k] from lane
+        // i + 32 k and B[k][j] from lane j + 32 k (float32 operands and accumulation).  The
+        // chunk sums in a fresh accumulator that is then added to the running sum.
+        {
+            f32x16 p1, p2;
 #pragma unroll
-        for (int k = 0; k < BK; ++k) {
-            const float4 av1 = *reinterpret_cast<const float4*>(&A1[k][ti]);
-            const float4 av2 = *reinterpret_cast<const float4*>(&A2[k][ti]);
-            const float4 bv1 = *reinterpret_cast<const float4*>(&B1[k][tj]);
-            const float4 bv2 = *reinterpret_cast<const float4*>(&B2[k][tj]);
-            const float a1[4] = {av1.x, av1.y, av1.z, av1.w}, a2[4] = {av2.x, av2.y, av2.z, av2.w};
-            const float b1[4] = {bv1.x, bv1.y, bv1.z, bv1.w}, b2[4] = {bv2.x, bv2.y, bv2.z, bv2.w};
+            for (int r = 0; r < 16; ++r) { p1[r] = 0.f; p2[r] = 0.f; }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    part1[u][v] = fmaf(a1[u], b1[v], part1[u][v]);
-                    part2[u][v] = fmaf(a2[u], b2[v], part2[u][v]);
-                }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                acc1[u][v] += part1[u][v];
-                acc2[u][v] += part2[u][v];
+            for (int kk = 0; kk < BK / 2; ++kk) {
+                const int k = 2 * kk + (lane >> 5);
+                p1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[k][32 * wi + (lane & 31)], B1[k][32 * wj + (lane & 31)],
+                                                          p1, 0, 0, 0);
+                p2 = __builtin_amdgcn_mfma_f32_32x32x2f32(A2[k][32 * wi + (lane & 31)], B2[k][32 * wj + (lane & 31)],
+                                                          p2, 0, 0, 0);
             }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) { acc1[r] += p1[r]; acc2[r] += p2[r]; }
+        }
         __syncthreads();
     }
-    // ---- stores: interleave (forward) or recombine (inverse) ------------------------------
+    // ---- stores: interleave (forward) or recombine (inverse).  Register r of the lane
+    // holds sub-tile row 8 (r / 4) + 4 (lane / 32) + r % 4, column lane % 32.
+    const int gj = j0 + 32 * wj + (lane & 31);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int gi = i0 + ti + u;
-        if (gi >= M) continue;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int gj = j0 + tj + v;
-            if (gj >= N) continue;
-            if (ROW) {
-                gfloat* dr = dst + (int64_t)gi * cols;
-                if (!INV) { dr[2 * gj] = acc1[u][v]; dr[2 * gj + 1] = acc2[u][v]; }
-                else { dr[gj] = acc1[u][v] + acc2[u][v]; dr[L - 1 - gj] = acc1[u][v] - acc2[u][v]; }
+    for (int r = 0; r < 16; ++r) {
+        const int gi = i0 + 32 * wi + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (gi >= M || gj >= N) continue;
+        if (ROW) {
+            gfloat* dr = dst + (int64_t)gi * cols;
+            if (!INV) { dr[2 * gj] = acc1[r]; dr[2 * gj + 1] = acc2[r]; }
+            else { dr[gj] = acc1[r] + acc2[r]; dr[L - 1 - gj] = acc1[r] - acc2[r]; }
+        } else {
+            if (!INV) {
+                dst[(int64_t)(2 * gi) * cols + gj] = acc1[r];
+                dst[(int64_t)(2 * gi + 1) * cols + gj] = acc2[r];
             } else {
-                if (!INV) {
-                    dst[(int64_t)(2 * gi) * cols + gj] = acc1[u][v];
-                    dst[(int64_t)(2 * gi + 1) * cols + gj] = acc2[u][v];
-                } else {
-                    dst[(int64_t)gi * cols + gj] = acc1[u][v] + acc2[u][v];
-                    dst[(int64_t)(L - 1 - gi) * cols + gj] = acc1[u][v] - acc2[u][v];
-                }
+                dst[(int64_t)gi * cols + gj] = acc1[r] + acc2[r];
+                dst[(int64_t)(L - 1 - gi) * cols + gj] = acc1[r] - acc2[r];
             }
         }
     }
