@@ -1,24 +1,25 @@
 // Float32 2D DCT kernels on the vector ALU (all sizes, the "plain FP32" path).
 //
 // Separable evaluation of eq. 2 (Section 2.1): a length-W transform along every row,
-// then a length-H transform along every column, each done by one thread on a vector
-// held in its registers (dct1d.hpp).  The paper's CPU organisation (Section 3.1,
-// Algorithm 1) copies rows into padded scratch of stride n+4, runs one pass per
-// lane, re-packs into bands and runs the other pass.  The GPU analogue here:
+// then a length-H transform along every column, each done on a vector held in registers
+// (dct1d.hpp).  The paper's CPU organisation (Section 3.1, Algorithm 1) copies rows into
+// padded scratch of stride n+4, runs one pass per lane, re-packs into bands and runs the
+// other pass.  The GPU analogues here keep each array on chip between the two passes, so
+// every element is read from HBM once and written once (the fused round trip runs the
+// forward and inverse column transforms back to back in registers; Prop. 1: no
+// intermediate correction):
 //
-//   fused kernel (rows, cols <= 128): a workgroup stages a tile of whole arrays in
-//   LDS with coalesced 16-byte global loads, using a padded row pitch of cols+4
-//   floats (so 16-byte row reads of consecutive rows and 4-byte column reads of
-//   consecutive columns fall in distinct banks), then
-//     row pass:    thread (array, r) reads row r from LDS, transforms, writes back
-//     column pass: thread (array, c) reads column c, transforms, writes back
-//   and the tile leaves through coalesced 16-byte stores.  One HBM read and one HBM
-//   write per element; the fused round trip runs forward columns and inverse
-//   columns back to back in registers (Prop. 1: no intermediate correction).
-//
-//   two-pass kernels (an axis of 256): the row pass and the column pass are separate
-//   launches over HBM (each thread owns a whole row or a whole column; column
-//   accesses are coalesced across the wavefront's consecutive columns).
+//   k_wave (rows, cols <= 64): one wavefront per tile of 64 / max(rows, cols) arrays;
+//     a lane transforms a row, the rows meet in an LDS tile, a lane transforms a
+//     column.  Variants stage the tile through LDS with coalesced 16-byte moves and
+//     cap the resident workgroups per CU (fewer bytes in flight per CU).
+//   k_fused (rows, cols <= 128): a workgroup stages a tile of whole arrays in LDS with
+//     a padded row pitch of cols + 4 and runs a row pass and a column pass there.
+//   k_split64 / k_split128 / k_split256: one workgroup per array, each transform shared
+//     by two halves of the workgroup through the top level of the even/odd recursion.
+//   k_rows / k_cols (an axis of 256 in a rectangle): the row pass and the column pass
+//     are separate launches over HBM (a thread owns a whole row or column; column
+//     accesses are coalesced across the wavefront's consecutive columns).
 #include "dct1d.hpp"
 #include "internal.hpp"
 
