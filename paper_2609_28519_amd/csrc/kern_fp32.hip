@@ -863,10 +863,12 @@ __device__ __forceinline__ void rows_fwd(const gfloat* src, float* T, int wid, f
         {
             float qa[64];
             load_colhalf<0>(src, wid, qa);
-            load_colhalf<1>(src, wid, qb);
             __syncthreads(); // earlier readers of the LDS are done
             put_colhalf(T, wid, qa);
         }
+        // the inner half is requested once the outer half has arrived: half an array in
+        // flight per CU at a time, its latency covered by the first row-read window
+        load_colhalf<1>(src, wid, qb);
         __syncthreads();
         rows_from_stage<G>(T, wid, v, 0);
         __syncthreads();
@@ -888,9 +890,9 @@ __device__ __forceinline__ void cols_inv(const gfloat* src, float* T, int wid, f
     {
         float qa[64], qb[64];
         load_rowhalf<0>(src, wid, qa);
-        load_rowhalf<1>(src, wid, qb);
         __syncthreads();
         put_rowhalf(T, wid, qa);
+        load_rowhalf<1>(src, wid, qb); // as in rows_fwd: half an array in flight at a time
         __syncthreads();
         int c = lane_t(wid) & 127;
 #pragma unroll
