@@ -1507,7 +1507,7 @@ int fp32_variant_count(int rows, int cols, int)
 // 64 x 64 the two-wavefront split kernel, with at most 4 workgroups per CU for forward and
 // inverse (other shapes with a 64 axis: staged, at most 4 per CU, uncapped for the round
 // trip).  The staged split kernel for 128 x 128 with one array per workgroup, the split
-// kernel for 256 x 256.
+// kernel for 256 x 256 with its two cohorts of CUs staggered by about 6 x 8k cycles.
 int fp32_default_variant(int rows, int cols, int dir)
 {
     if (rows <= 64 && cols <= 64) {
@@ -1517,6 +1517,7 @@ int fp32_default_variant(int rows, int cols, int dir)
         return m <= 8 ? 4 : m <= 16 ? 6 : m <= 32 ? (rt ? 8 : 7) : (rt ? 4 : 12);
     }
     if (rows == 128 && cols == 128) return 4;
+    if (rows == 256 && cols == 256) return 4;
     return 0;
 }
 
