@@ -372,148 +372,158 @@ constexpr int S128_P = 129;
 // STAGE: the forward rows (inverse columns) come from an LDS copy of the array (row pitch
 // 132) filled with coalesced 16-byte loads (each wavefront instruction covers two whole
 // rows) instead of each thread reading its own row (column) from HBM.
+// One array, as seen by the wavefronts of one role (each role runs its own straight-line
+// code; both pass the same barriers).
+template <int DIR, bool STAGE, int ROLE>
+__device__ __forceinline__ void s128_array(const Addr& a, int64_t blk, float* T, const float2* tw_in, int t)
+{
+    constexpr int L = 128, H = 64, P = S128_P, SP = 132;
+    constexpr int role = ROLE; // 0: even half, 1: odd half
+    const int idx = t & 127;   // row or column handled by this thread
+    twptr tw = per_iteration(tw_in);
+    const gfloat* src = a.src(blk);
+    gfloat* dst = a.dst(blk);
+    float v[H], o[H];
+    if (DIR != DCT2D_INVERSE) {
+        // ---- forward rows: row idx ------------------------------------------------
+        if (STAGE) {
+            // (the previous array's last LDS reads precede its final barrier)
+            const DCT_GLOBAL char* sb = reinterpret_cast<const DCT_GLOBAL char*>(uniform_ptr(src));
+            float q[64];
+#pragma unroll
+            for (int it = 0; it < 16; ++it) {
+                const float4 w = *reinterpret_cast<const gfloat4*>(sb + (uint32_t)((it * 256 + t) * 16));
+                q[4 * it] = w.x; q[4 * it + 1] = w.y; q[4 * it + 2] = w.z; q[4 * it + 3] = w.w;
+            }
+#pragma unroll
+            for (int it = 0; it < 16; ++it) {
+                const int f = it * 256 + t; // row f / 32, columns 4 (f % 32) .. +3
+                *reinterpret_cast<float4*>(&T[(f >> 5) * SP + 4 * (f & 31)]) =
+                    make_float4(q[4 * it], q[4 * it + 1], q[4 * it + 2], q[4 * it + 3]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < H / 4; ++j) {
+                const float4 lo = *reinterpret_cast<const float4*>(&T[idx * SP + 4 * j]);
+                const float4 hi = *reinterpret_cast<const float4*>(&T[idx * SP + L - 4 - 4 * j]);
+                const float xl[4] = {lo.x, lo.y, lo.z, lo.w};
+                const float xh[4] = {hi.w, hi.z, hi.y, hi.x}; // x[127 - (4j + i)]
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[4 * j + i] = role == 0 ? xl[i] + xh[i] : xl[i] - xh[i];
+            }
+            __syncthreads(); // the staged copy is read before the tile overwrites it
+        } else {
+            const gfloat* row = src + (int64_t)idx * L;
+#pragma unroll
+            for (int j = 0; j < H / 4; ++j) {
+                const float4 lo = *reinterpret_cast<const gfloat4*>(row + 4 * j);
+                const float4 hi = *reinterpret_cast<const gfloat4*>(row + L - 4 - 4 * j);
+                const float xl[4] = {lo.x, lo.y, lo.z, lo.w};
+                const float xh[4] = {hi.w, hi.z, hi.y, hi.x}; // x[127 - (4j + i)]
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[4 * j + i] = role == 0 ? xl[i] + xh[i] : xl[i] - xh[i];
+            }
+        }
+        if (role == 0) dct2_rec<L, H>(v, o, tw); else dct4_scaled<L, H>(v, o, tw);
+#pragma unroll
+        for (int k = 0; k < H; ++k) T[idx * P + 2 * k + role] = o[k];
+        __syncthreads();
+        // ---- forward columns: column idx from LDS ---------------------------------
+#pragma unroll
+        for (int n = 0; n < H; ++n) {
+            const float xl = T[n * P + idx], xh = T[(L - 1 - n) * P + idx];
+            v[n] = role == 0 ? xl + xh : xl - xh;
+        }
+        if (role == 0) dct2_rec<L, H>(v, o, tw); else dct4_scaled<L, H>(v, o, tw);
+        if (DIR == DCT2D_FORWARD) {
+#pragma unroll
+            for (int k = 0; k < H; ++k) dst[(int64_t)(2 * k + role) * L + idx] = o[k];
+            __syncthreads(); // LDS reuse by the next array
+            return;
+        }
+        // round trip: inverse columns on the same data (even -> DCT-III_64, odd -> DCT-IV_64)
+        asm volatile("" : "+s"(tw));
+        if (role == 0) dct3_rec<L, H>(o, v, tw); else dct4_scaled<L, H>(o, v, tw);
+        __syncthreads(); // every column read before the halves overwrite it
+#pragma unroll
+        for (int n = 0; n < H; ++n) T[(role * H + n) * P + idx] = v[n];
+    } else {
+        // ---- inverse columns: even (role 0) or odd (role 1) coefficient rows
+        if (STAGE) {
+            // coalesced 16-byte loads into an LDS copy (pitch 132), then column idx from it
+            const DCT_GLOBAL char* sb = reinterpret_cast<const DCT_GLOBAL char*>(uniform_ptr(src));
+            float q[64];
+#pragma unroll
+            for (int it = 0; it < 16; ++it) {
+                const float4 w = *reinterpret_cast<const gfloat4*>(sb + (uint32_t)((it * 256 + t) * 16));
+                q[4 * it] = w.x; q[4 * it + 1] = w.y; q[4 * it + 2] = w.z; q[4 * it + 3] = w.w;
+            }
+#pragma unroll
+            for (int it = 0; it < 16; ++it) {
+                const int f = it * 256 + t;
+                *reinterpret_cast<float4*>(&T[(f >> 5) * SP + 4 * (f & 31)]) =
+                    make_float4(q[4 * it], q[4 * it + 1], q[4 * it + 2], q[4 * it + 3]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < H; ++k) o[k] = T[(2 * k + role) * SP + idx];
+            __syncthreads(); // the staged copy is read before the halves overwrite it
+        } else {
+#pragma unroll
+            for (int k = 0; k < H; ++k) o[k] = src[(int64_t)(2 * k + role) * L + idx];
+        }
+        if (role == 0) dct3_rec<L, H>(o, v, tw); else dct4_scaled<L, H>(o, v, tw);
+#pragma unroll
+        for (int n = 0; n < H; ++n) T[(role * H + n) * P + idx] = v[n];
+    }
+    __syncthreads();
+    // ---- inverse rows.  LDS holds the column results as halves: rows 0..63 = a,
+    // rows 64..127 = b, with Z[n] = a[n] + b[n], Z[127-n] = a[n] - b[n].
+    {
+        const bool top = idx < H;
+        const int rr = top ? idx : L - 1 - idx;
+        const float sg = top ? 1.f : -1.f;
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const int c = 2 * k + role;
+            o[k] = T[rr * P + c] + sg * T[(H + rr) * P + c];
+        }
+    }
+    if (role == 0) dct3_rec<L, H>(o, v, tw); else dct4_scaled<L, H>(o, v, tw);
+    __syncthreads(); // all reads of the column halves done
+#pragma unroll
+    for (int n = 0; n < H; ++n) T[idx * P + role * H + n] = v[n];
+    __syncthreads();
+    // ---- store: x[r][n] = a[n] + b[n], x[r][127-n] = a[n] - b[n].  Lane t covers column
+    // t % 128 of rows 2i + t / 128: consecutive lanes read consecutive LDS words (no bank
+    // conflicts) and write 256-byte segments.
+    {
+        int c = t & (L - 1);
+        asm volatile("" : "+v"(c)); // per array: keeps the 128 offsets below out of the loop preheader
+        const int cs = c < H ? c : L - 1 - c;
+        const float sg = c < H ? 1.f : -1.f; // exact: one rounding, as a +- b
+        DCT_GLOBAL char* db = reinterpret_cast<DCT_GLOBAL char*>(uniform_ptr(dst));
+#pragma unroll
+        for (int i = 0; i < L / 2; ++i) {
+            const int r = 2 * i + (t >> 7);
+            *reinterpret_cast<gfloat*>(db + (uint32_t)((r * L + c) * 4)) =
+                __builtin_fmaf(sg, T[r * P + H + cs], T[r * P + cs]);
+        }
+    }
+    __syncthreads();
+}
+
 template <int DIR, bool STAGE>
 __global__ void __launch_bounds__(256, 2) // two workgroups per CU: the LDS tile allows exactly two
 k_split128(Addr a, int64_t batch, const float2* __restrict__ tw_in)
 {
-    constexpr int L = 128, H = 64, P = S128_P, SP = 132;
+    constexpr int L = 128, P = S128_P, SP = 132;
     __shared__ float4 T4[(STAGE ? L * SP : L * P) / 4];
     float* const T = reinterpret_cast<float*>(T4);
     const int t = threadIdx.x;
-    const int role = t >> 7;       // 0: even half, 1: odd half (uniform per wavefront)
-    const int idx = t & 127;       // row or column handled by this thread
+    const bool odd = t >= 128; // the role (uniform per wavefront)
     for (int64_t blk = blockIdx.x; blk < batch; blk += gridDim.x) {
-        twptr tw = per_iteration(tw_in);
-        const gfloat* src = a.src(blk);
-        gfloat* dst = a.dst(blk);
-        float v[H], o[H];
-        if (DIR != DCT2D_INVERSE) {
-            // ---- forward rows: row idx ------------------------------------------------
-            if (STAGE) {
-                // (the previous array's last LDS reads precede its final barrier)
-                const DCT_GLOBAL char* sb = reinterpret_cast<const DCT_GLOBAL char*>(uniform_ptr(src));
-                float q[64];
-#pragma unroll
-                for (int it = 0; it < 16; ++it) {
-                    const float4 w = *reinterpret_cast<const gfloat4*>(sb + (uint32_t)((it * 256 + t) * 16));
-                    q[4 * it] = w.x; q[4 * it + 1] = w.y; q[4 * it + 2] = w.z; q[4 * it + 3] = w.w;
-                }
-#pragma unroll
-                for (int it = 0; it < 16; ++it) {
-                    const int f = it * 256 + t; // row f / 32, columns 4 (f % 32) .. +3
-                    *reinterpret_cast<float4*>(&T[(f >> 5) * SP + 4 * (f & 31)]) =
-                        make_float4(q[4 * it], q[4 * it + 1], q[4 * it + 2], q[4 * it + 3]);
-                }
-                __syncthreads();
-#pragma unroll
-                for (int j = 0; j < H / 4; ++j) {
-                    const float4 lo = *reinterpret_cast<const float4*>(&T[idx * SP + 4 * j]);
-                    const float4 hi = *reinterpret_cast<const float4*>(&T[idx * SP + L - 4 - 4 * j]);
-                    const float xl[4] = {lo.x, lo.y, lo.z, lo.w};
-                    const float xh[4] = {hi.w, hi.z, hi.y, hi.x}; // x[127 - (4j + i)]
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) v[4 * j + i] = role == 0 ? xl[i] + xh[i] : xl[i] - xh[i];
-                }
-                __syncthreads(); // the staged copy is read before the tile overwrites it
-            } else {
-                const gfloat* row = src + (int64_t)idx * L;
-#pragma unroll
-                for (int j = 0; j < H / 4; ++j) {
-                    const float4 lo = *reinterpret_cast<const gfloat4*>(row + 4 * j);
-                    const float4 hi = *reinterpret_cast<const gfloat4*>(row + L - 4 - 4 * j);
-                    const float xl[4] = {lo.x, lo.y, lo.z, lo.w};
-                    const float xh[4] = {hi.w, hi.z, hi.y, hi.x}; // x[127 - (4j + i)]
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) v[4 * j + i] = role == 0 ? xl[i] + xh[i] : xl[i] - xh[i];
-                }
-            }
-            if (role == 0) dct2_rec<L, H>(v, o, tw); else dct4_scaled<L, H>(v, o, tw);
-#pragma unroll
-            for (int k = 0; k < H; ++k) T[idx * P + 2 * k + role] = o[k];
-            __syncthreads();
-            // ---- forward columns: column idx from LDS ---------------------------------
-#pragma unroll
-            for (int n = 0; n < H; ++n) {
-                const float xl = T[n * P + idx], xh = T[(L - 1 - n) * P + idx];
-                v[n] = role == 0 ? xl + xh : xl - xh;
-            }
-            if (role == 0) dct2_rec<L, H>(v, o, tw); else dct4_scaled<L, H>(v, o, tw);
-            if (DIR == DCT2D_FORWARD) {
-#pragma unroll
-                for (int k = 0; k < H; ++k) dst[(int64_t)(2 * k + role) * L + idx] = o[k];
-                __syncthreads(); // LDS reuse by the next array
-                continue;
-            }
-            // round trip: inverse columns on the same data (even -> DCT-III_64, odd -> DCT-IV_64)
-            asm volatile("" : "+s"(tw));
-            if (role == 0) dct3_rec<L, H>(o, v, tw); else dct4_scaled<L, H>(o, v, tw);
-            __syncthreads(); // every column read before the halves overwrite it
-#pragma unroll
-            for (int n = 0; n < H; ++n) T[(role * H + n) * P + idx] = v[n];
-        } else {
-            // ---- inverse columns: even (role 0) or odd (role 1) coefficient rows
-            if (STAGE) {
-                // coalesced 16-byte loads into an LDS copy (pitch 132), then column idx from it
-                const DCT_GLOBAL char* sb = reinterpret_cast<const DCT_GLOBAL char*>(uniform_ptr(src));
-                float q[64];
-#pragma unroll
-                for (int it = 0; it < 16; ++it) {
-                    const float4 w = *reinterpret_cast<const gfloat4*>(sb + (uint32_t)((it * 256 + t) * 16));
-                    q[4 * it] = w.x; q[4 * it + 1] = w.y; q[4 * it + 2] = w.z; q[4 * it + 3] = w.w;
-                }
-#pragma unroll
-                for (int it = 0; it < 16; ++it) {
-                    const int f = it * 256 + t;
-                    *reinterpret_cast<float4*>(&T[(f >> 5) * SP + 4 * (f & 31)]) =
-                        make_float4(q[4 * it], q[4 * it + 1], q[4 * it + 2], q[4 * it + 3]);
-                }
-                __syncthreads();
-#pragma unroll
-                for (int k = 0; k < H; ++k) o[k] = T[(2 * k + role) * SP + idx];
-                __syncthreads(); // the staged copy is read before the halves overwrite it
-            } else {
-#pragma unroll
-                for (int k = 0; k < H; ++k) o[k] = src[(int64_t)(2 * k + role) * L + idx];
-            }
-            if (role == 0) dct3_rec<L, H>(o, v, tw); else dct4_scaled<L, H>(o, v, tw);
-#pragma unroll
-            for (int n = 0; n < H; ++n) T[(role * H + n) * P + idx] = v[n];
-        }
-        __syncthreads();
-        // ---- inverse rows.  LDS holds the column results as halves: rows 0..63 = a,
-        // rows 64..127 = b, with Z[n] = a[n] + b[n], Z[127-n] = a[n] - b[n].
-        {
-            const bool top = idx < H;
-            const int rr = top ? idx : L - 1 - idx;
-            const float sg = top ? 1.f : -1.f;
-#pragma unroll
-            for (int k = 0; k < H; ++k) {
-                const int c = 2 * k + role;
-                o[k] = T[rr * P + c] + sg * T[(H + rr) * P + c];
-            }
-        }
-        if (role == 0) dct3_rec<L, H>(o, v, tw); else dct4_scaled<L, H>(o, v, tw);
-        __syncthreads(); // all reads of the column halves done
-#pragma unroll
-        for (int n = 0; n < H; ++n) T[idx * P + role * H + n] = v[n];
-        __syncthreads();
-        // ---- store: x[r][n] = a[n] + b[n], x[r][127-n] = a[n] - b[n].  Lane t covers column
-        // t % 128 of rows 2i + t / 128: consecutive lanes read consecutive LDS words (no bank
-        // conflicts) and write 256-byte segments.
-        {
-            int c = t & (L - 1);
-            asm volatile("" : "+v"(c)); // per array: keeps the 128 offsets below out of the loop preheader
-            const int cs = c < H ? c : L - 1 - c;
-            const float sg = c < H ? 1.f : -1.f; // exact: one rounding, as a +- b
-            DCT_GLOBAL char* db = reinterpret_cast<DCT_GLOBAL char*>(uniform_ptr(dst));
-#pragma unroll
-            for (int i = 0; i < L / 2; ++i) {
-                const int r = 2 * i + (t >> 7);
-                *reinterpret_cast<gfloat*>(db + (uint32_t)((r * L + c) * 4)) =
-                    __builtin_fmaf(sg, T[r * P + H + cs], T[r * P + cs]);
-            }
-        }
-        __syncthreads();
+        if (odd) s128_array<DIR, STAGE, 1>(a, blk, T, tw_in, t); else s128_array<DIR, STAGE, 0>(a, blk, T, tw_in, t);
     }
 }
 
