@@ -54,7 +54,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the batched transform needs no communication, "
-              "a multi-GPU run would be N independent copies of this one (see DESIGN.md).", file=sys.stderr)
+              "a multi-GPU run would be N independent copies of this one, each on its share of the "
+              "arrays.", file=sys.stderr)
         sys.exit(2)
     import torch
 
