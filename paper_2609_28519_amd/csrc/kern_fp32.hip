@@ -160,14 +160,14 @@ struct WaveCfg {
     static_assert(TB <= 64, "one wavefront per tile");
     static constexpr int BPW = 64 / TB;
     // Rows of 16 or more floats are stored unpadded, with the 16-byte groups of row r
-    // XOR-permuted by a row key: the 16 rows that one 16-lane phase of a lane-per-row
-    // 16-byte access touches land on 16 different group positions of the 64 banks, a
+    // XOR-permuted by a row key: the 8 rows that one 8-lane phase of a lane-per-row
+    // 16-byte access touches land on 8 different group positions of the 32 banks, a
     // lane-per-column 4-byte access reads a permutation of one row, and an array takes
     // exactly H*W floats (which raises the number of resident workgroups where LDS is the
     // limit).  Rows of 8 use the padded pitch 12.
     static constexpr bool SWZ = W >= 16;
     static constexpr int G = W / 4;                  // 16-byte groups per row
-    static constexpr int RPL = W >= 64 ? 1 : 64 / W; // rows per 64-bank line
+    static constexpr int RPL = W >= 32 ? 1 : 32 / W; // rows per 32-bank line
     static constexpr int P = SWZ ? W : W + 4;
     static constexpr int HP = H * P;
     // array pitch: the arrays of one wavefront start in different banks
