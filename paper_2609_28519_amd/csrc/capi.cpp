@@ -137,7 +137,10 @@ int dct::dispatch(const DeviceTables* t, Job j, int prec)
 {
     const int p = resolve_precision(j.rows, j.cols, j.dir, prec);
     j.variant = variant_for(j.rows, j.cols, j.dir, p);
-    if (p == DCT2D_FP32) return launch_fp32(t, j);
+    if (p == DCT2D_FP32) {
+        if (j.shared) j.variant = fp32_unshared_variant(j.rows, j.cols, j.variant);
+        return launch_fp32(t, j);
+    }
     if (!mfma_supported(j.rows, j.cols, p)) return DCT2D_ERR_PRECISION;
     return launch_mfma(t, j, p);
 }

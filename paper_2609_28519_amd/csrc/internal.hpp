@@ -131,6 +131,7 @@ struct Job {
     const int64_t* out_idx = nullptr;
     float* const* in_slot = nullptr;  // optional device-resident base pointers
     float* const* out_slot = nullptr;
+    bool shared = false;              // launched beside other kernels (a ragged plan's branch)
     Addr addr() const { return Addr{in, out, in_stride, out_stride, in_idx, out_idx, in_slot, out_slot}; }
 };
 
@@ -146,6 +147,7 @@ int launch_dense_axis(const Addr& a, int64_t count, int rows, int cols, bool col
 int launch_fp32(const DeviceTables* t, const Job& j);
 int fp32_variant_count(int rows, int cols, int dir);
 int fp32_default_variant(int rows, int cols, int dir);
+int fp32_unshared_variant(int rows, int cols, int variant);
 
 int launch_mfma(const DeviceTables* t, const Job& j, int precision);
 int mfma_supported(int rows, int cols, int precision);

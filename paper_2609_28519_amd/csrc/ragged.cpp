@@ -4,7 +4,8 @@
 // Plan creation (host, once): the descriptors are validated and grouped into shape
 // classes; each class gets a device-resident list of element offsets and the kernel
 // configuration of the frozen per-size policy (the same table the autotuner fills for
-// the basic calls, Section 3.2: variants fixed before measurement).  Image classes
+// the basic calls, Section 3.2: variants fixed before measurement), with grid-stride
+// schedules replaced by one tile per workgroup, since the classes share the GPU.  Image classes
 // whose axes the fast transforms do not cover (non-powers of two such as 384, or axes
 // above 256) get dense float32 Q tables and a workspace.  The whole batch is then
 // recorded once into a HIP graph: one fork-join branch per class, so independent
@@ -89,6 +90,7 @@ int record_class(const DeviceTables* t, dct2d_ragged_plan* p, const ClassRec& c,
         Job j{p->dir, nullptr, nullptr, c.count, c.rows, c.cols, 0, 0, s, 0};
         j.in_idx = j.out_idx = c.d_off;
         j.in_slot = j.out_slot = p->d_slot;
+        j.shared = true; // the classes run as concurrent branches of the graph
         return dispatch(t, j, p->prec);
     }
     // dense image passes: base(indexed) <-> workspace(packed), ping-pong
