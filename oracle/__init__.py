@@ -7,7 +7,7 @@ generators (``workloads``), which hold no transform arithmetic.
 
 The arithmetic lives in ``dct_oracle.c`` (plain C, double precision, the
 direct definition of the paper's Section 2.1 eq. 1-2 evaluated as two matrix
-products).  This module builds it with gcc on first use, wraps it with ctypes
+products; the spectral filter of Prop. 1 / eq. 4 as forward, multiply, inverse).  This module builds it with gcc on first use, wraps it with ctypes
 and adds the acceptance metric of Section 6 eq. 5.
 """
 from __future__ import annotations
@@ -49,6 +49,8 @@ class Oracle:
             fn = getattr(lib, name)
             fn.argtypes = [vp, vp, i64, i32, i32, i64, i32]
             fn.restype = ctypes.c_int
+        lib.oracle_filter.argtypes = [vp, vp, i64, i32, i32, i64, vp, i64, i32]
+        lib.oracle_filter.restype = ctypes.c_int
         lib.oracle_qmatrix.argtypes = [i32, vp]
         lib.oracle_qmatrix.restype = ctypes.c_int
         self.lib = lib
@@ -95,6 +97,32 @@ class Oracle:
         """inverse(forward(X)) computed in double (exact result: X itself)."""
         return self._run("oracle_roundtrip", x, threads)
 
+    def filter(self, x: np.ndarray, lam: np.ndarray, threads: int | None = None) -> np.ndarray:
+        """Q_h^T (L o (Q_h X Q_w^T)) Q_w per array (Prop. 1, eq. 4), in double.
+
+        x: float32 (batch, rows, cols) or (rows, cols).  lam: (rows, cols) for one
+        operator shared by every array, or (batch, rows, cols) for one per array;
+        promoted to double exactly.
+        """
+        squeeze = x.ndim == 2
+        xb = np.ascontiguousarray(x[None] if squeeze else x)
+        if xb.dtype != np.float32 or xb.ndim != 3:
+            raise TypeError("filter takes float32 (batch, rows, cols) input")
+        b, h, w = xb.shape
+        lm = np.ascontiguousarray(lam, dtype=np.float64)
+        if lm.shape == (h, w):
+            lam_stride = 0
+        elif lm.shape == (b, h, w):
+            lam_stride = h * w
+        else:
+            raise ValueError("lam must be (rows, cols) or (batch, rows, cols)")
+        y = np.empty((b, h, w), dtype=np.float64)
+        rc = self.lib.oracle_filter(xb.ctypes.data, y.ctypes.data, b, h, w, h * w, lm.ctypes.data,
+                                    lam_stride, threads or default_threads())
+        if rc != 0:
+            raise RuntimeError("oracle_filter failed with %d" % rc)
+        return y[0] if squeeze else y
+
 
 def _default() -> Oracle:
     global _lib
@@ -129,6 +157,11 @@ def inverse(y: np.ndarray, threads: int | None = None) -> np.ndarray:
 def roundtrip(x: np.ndarray, threads: int | None = None) -> np.ndarray:
     """inverse(forward(X)) computed in double (exact result: X itself)."""
     return _default().roundtrip(x, threads)
+
+
+def filter(x: np.ndarray, lam: np.ndarray, threads: int | None = None) -> np.ndarray:
+    """Q_h^T (L o (Q_h X Q_w^T)) Q_w per array (Prop. 1, eq. 4), in double."""
+    return _default().filter(x, lam, threads)
 
 
 def e_rel(yhat: np.ndarray, y: np.ndarray, x: np.ndarray) -> np.ndarray:

@@ -10,6 +10,9 @@
  *   (Q_n)_{kj} = a_k cos(pi/n (j + 1/2) k),  a_0 = n^{-1/2},  a_k = (2/n)^{1/2}
  *   forward  C(X)    = Q_h X Q_w^T
  *   inverse  C^-1(Y) = Q_h^T Y Q_w
+ *   filter   C^-1(L o C(X)) for a diagonal spectral operator given as an array L of
+ *            multipliers, L[k][l] scaling coefficient (k, l) (Section 2.1, Prop. 1,
+ *            eq. 4, with the orthonormal Q in place of the scaled core and E = I)
  * evaluated exactly as written: the two matrix products one after the other,
  * plain loops, double precision throughout, output kept in double (never
  * rounded to float).  No fast algorithm, no blocking, no fusion.
@@ -60,7 +63,7 @@ int oracle_qmatrix(int32_t n, double* q)
 }
 
 typedef struct {
-    int dir;                 /* 0 forward, 1 inverse, 2 inverse(forward(.)) */
+    int dir;                 /* 0 forward, 1 inverse, 2 inverse(forward(.)), 3 filter */
     const float* xf;         /* float input (or NULL) */
     const double* xd;        /* double input (or NULL) */
     double* y;               /* output, packed rows*cols per array */
@@ -68,6 +71,8 @@ typedef struct {
     int32_t rows, cols;
     const double* qh;        /* Q_rows */
     const double* qw;        /* Q_cols */
+    const double* lam;       /* filter multipliers: array b uses lam + b*lam_stride */
+    int64_t lam_stride;
     int64_t next;            /* shared work counter (protected by lock) */
     pthread_mutex_t lock;
     int failed;
@@ -140,8 +145,15 @@ static void* worker(void* arg)
             forward_one(in, out, t, job->rows, job->cols, job->qh, job->qw);
         } else if (job->dir == 1) {
             inverse_one(in, out, t, job->rows, job->cols, job->qh, job->qw);
-        } else {
+        } else if (job->dir == 2) {
             forward_one(in, t2, t, job->rows, job->cols, job->qh, job->qw);
+            inverse_one(t2, out, t, job->rows, job->cols, job->qh, job->qw);
+        } else {
+            /* Prop. 1: forward, the diagonal operator (one multiplier per
+             * coefficient), then the adjoint; all in double */
+            const double* lam = job->lam + b * job->lam_stride;
+            forward_one(in, t2, t, job->rows, job->cols, job->qh, job->qw);
+            for (int64_t i = 0; i < n; ++i) t2[i] *= lam[i];
             inverse_one(t2, out, t, job->rows, job->cols, job->qh, job->qw);
         }
     }
@@ -150,9 +162,12 @@ static void* worker(void* arg)
 }
 
 static int run(int dir, const float* xf, const double* xd, double* y, int64_t batch,
-               int32_t rows, int32_t cols, int64_t stride, int32_t nthreads)
+               int32_t rows, int32_t cols, int64_t stride, int32_t nthreads,
+               const double* lam, int64_t lam_stride)
 {
     if (batch < 0 || rows <= 0 || cols <= 0 || (batch > 0 && (y == NULL || (!xf && !xd))))
+        return ORACLE_ERR_ARG;
+    if (dir == 3 && (lam == NULL || lam_stride < 0 || (lam_stride > 0 && lam_stride < (int64_t)rows * cols)))
         return ORACLE_ERR_ARG;
     if (stride < (int64_t)rows * cols) return ORACLE_ERR_ARG;
     if (batch == 0) return ORACLE_OK;
@@ -165,6 +180,7 @@ static int run(int dir, const float* xf, const double* xd, double* y, int64_t ba
     job.dir = dir; job.xf = xf; job.xd = xd; job.y = y;
     job.batch = batch; job.stride = stride; job.rows = rows; job.cols = cols;
     job.qh = qh; job.qw = qw; job.next = 0; job.failed = 0;
+    job.lam = lam; job.lam_stride = lam_stride;
     pthread_mutex_init(&job.lock, NULL);
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
@@ -186,32 +202,42 @@ static int run(int dir, const float* xf, const double* xd, double* y, int64_t ba
 int oracle_forward(const float* x, double* y, int64_t batch, int32_t rows, int32_t cols,
                    int64_t stride, int32_t nthreads)
 {
-    return run(0, x, NULL, y, batch, rows, cols, stride, nthreads);
+    return run(0, x, NULL, y, batch, rows, cols, stride, nthreads, NULL, 0);
 }
 
 /* Inverse 2D DCT-III (eq. 2): X = Q_h^T Y Q_w.  Same layout rules as above. */
 int oracle_inverse(const float* x, double* y, int64_t batch, int32_t rows, int32_t cols,
                    int64_t stride, int32_t nthreads)
 {
-    return run(1, x, NULL, y, batch, rows, cols, stride, nthreads);
+    return run(1, x, NULL, y, batch, rows, cols, stride, nthreads, NULL, 0);
 }
 
 /* inverse(forward(X)) in double, both products of each kept in double. */
 int oracle_roundtrip(const float* x, double* y, int64_t batch, int32_t rows, int32_t cols,
                      int64_t stride, int32_t nthreads)
 {
-    return run(2, x, NULL, y, batch, rows, cols, stride, nthreads);
+    return run(2, x, NULL, y, batch, rows, cols, stride, nthreads, NULL, 0);
 }
 
 /* Double-input variants (for exact test inputs). */
 int oracle_forward_d(const double* x, double* y, int64_t batch, int32_t rows, int32_t cols,
                      int64_t stride, int32_t nthreads)
 {
-    return run(0, NULL, x, y, batch, rows, cols, stride, nthreads);
+    return run(0, NULL, x, y, batch, rows, cols, stride, nthreads, NULL, 0);
 }
 
 int oracle_inverse_d(const double* x, double* y, int64_t batch, int32_t rows, int32_t cols,
                      int64_t stride, int32_t nthreads)
 {
-    return run(1, NULL, x, y, batch, rows, cols, stride, nthreads);
+    return run(1, NULL, x, y, batch, rows, cols, stride, nthreads, NULL, 0);
+}
+
+/* Spectral filter of `batch` float32 arrays (layout as oracle_forward):
+ * y = Q_h^T (L o (Q_h X Q_w^T)) Q_w with L the rows x cols multipliers at
+ * lam + b*lam_stride (lam_stride 0: one operator for every array, else
+ * >= rows*cols).  Section 2.1, Prop. 1, eq. 4 (orthonormal form). */
+int oracle_filter(const float* x, double* y, int64_t batch, int32_t rows, int32_t cols,
+                  int64_t stride, const double* lam, int64_t lam_stride, int32_t nthreads)
+{
+    return run(3, x, NULL, y, batch, rows, cols, stride, nthreads, lam, lam_stride);
 }

@@ -15,6 +15,7 @@ import pytest
 import scipy.fft
 
 import oracle
+from tests.test_oracle_filter import neumann_laplacian, poisson_multipliers
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(os.path.dirname(HERE), "oracle", "dct_oracle.c")
@@ -31,6 +32,10 @@ MUTATIONS = {
                      "for (int32_t c = 0; c < w - 1; ++c) s += x"),
     "wrong_quadrant_sign": ("sign = -1.0", "sign = 1.0"),
     "zero_not_exact": ("if (m == n) return 0.0;", "if (m == n) return 1e-9;"),
+    "filter_multiplier_transposed": ("t2[i] *= lam[i];",
+                                     "t2[i] *= lam[(i % job->cols) * job->rows + i / job->cols];"),
+    "filter_multiplier_dropped": ("t2[i] *= lam[i];", "t2[i] *= 1.0;"),
+    "filter_per_array_operator_ignored": ("job->lam + b * job->lam_stride", "job->lam"),
 }
 
 
@@ -58,6 +63,20 @@ def _pins_pass(orc: oracle.Oracle) -> bool:
         if np.abs(orc.inverse(x) - xs).max() > 1e-12 * np.abs(xs).max():
             return False
         if np.abs(orc.roundtrip(x) - xd).max() > 1e-13:
+            return False
+    # the spectral filter: Neumann Poisson solve (test_oracle_filter.py)
+    for h, w in ((8, 32), (32, 8)):
+        x = g.standard_normal((3, h, w)).astype(np.float32)
+        xd = x.astype(np.float64)
+        lam = poisson_multipliers(h, w)
+        for op in (lam, np.broadcast_to(lam, (3, h, w)).copy()):
+            u = orc.filter(x, op)
+            r = neumann_laplacian(u) - (xd - xd.mean(axis=(1, 2), keepdims=True))
+            if not np.all(np.isfinite(r)) or np.abs(r).max() > 1e-11 * np.abs(xd).max() * 64:
+                return False
+        # one constant operator per array: array b scaled by c[b]
+        c = np.array([1.0, -2.0, 0.5])[:, None, None] * np.ones((3, h, w))
+        if np.abs(orc.filter(x, c) - c * xd).max() > 1e-12 * np.abs(xd).max():
             return False
     return True
 
