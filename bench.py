@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--save-policy", default="", help="write the tuned policy (autotune cache, JSON) here")
     ap.add_argument("--load-policy", default="", help="freeze this saved policy instead of tuning")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch (one graph launch) measurement")
+    ap.add_argument("--no-filter", action="store_true", help="skip the spectral-filter measurement")
     return ap.parse_args()
 
 
@@ -191,6 +192,7 @@ def main():
             compare.setdefault(p, {})[str(n)] = round(8 * n * n * host[n].shape[0] / (ms * 1e-3) / 1e9, 1)
             del scratch
 
+    filt = None if args.no_filter else filter_rates(dct, bufs, host, sizes, stream, per)
     ragged = None if args.no_ragged else ragged_c4(dct, stream, args.steps)
     copy_gbs = copy_ceiling(bufs[sizes[0]], stream)
     for n in sizes:
@@ -207,12 +209,50 @@ def main():
                       "precision": args.precision, "variants": tuned},
            "hbm_frac": round(value / HBM_PEAK_GBS, 4), "copy_ceiling_GBps": round(copy_gbs, 1),
            "wall_s": round(wall, 3),
-           "roofline": roofline, "per_size": per, "compare_forward_GBps": compare, "ragged_c4": ragged}
+           "roofline": roofline, "per_size": per, "compare_forward_GBps": compare, "ragged_c4": ragged,
+           "filter": filt}
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same arrays -----------
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(host, sizes, args.cpu_frac, bufs, stream)
     print(json.dumps(out), flush=True)
+
+
+def poisson_multipliers(n):
+    """Neumann Poisson solve on an n x n grid: 1 / (2 cos(pi k/n) + 2 cos(pi l/n) - 4), 0 at (0, 0)."""
+    k = np.arange(n)[:, None]
+    l = np.arange(n)[None, :]
+    mu = 2.0 * np.cos(np.pi * k / n) + 2.0 * np.cos(np.pi * l / n) - 4.0
+    lam = np.zeros((n, n))
+    lam[mu != 0] = 1.0 / mu[mu != 0]
+    return lam.astype(np.float32)
+
+
+def filter_rates(dct, bufs, host, sizes, stream, per, reps=5):
+    """The fused spectral filter (Prop. 1, eq. 4) on the same batches, one shared Poisson
+    operator, out of place: one read and one write per array like the round trip, so its
+    GB/s uses the same 8 N^2 bytes per array.  Reported beside the step, not part of it."""
+    import torch
+    res = {}
+    for n in sizes:
+        lam = torch.from_numpy(poisson_multipliers(n)).to(bufs[n].device)
+        scratch = torch.empty_like(bufs[n])
+        dct.filter(bufs[n], lam, out=scratch, stream=stream)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            dct.filter(bufs[n], lam, out=scratch, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        gbs = 8 * n * n * host[n].shape[0] / (ms * 1e-3) / 1e9
+        res[str(n)] = {"ms": round(ms, 4), "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                       "vs_roundtrip": round(gbs / per[str(n)]["roundtrip"]["GB/s"], 3)}
+        del scratch
+    torch.cuda.empty_cache()
+    return res
 
 
 def copy_ceiling(buf, stream, reps=10):

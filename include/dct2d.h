@@ -127,6 +127,30 @@ int dct2d_transform_ex(int dir, const float* in, float* out, int64_t batch, int3
                        int32_t cols, int64_t in_stride, int64_t out_stride, int precision,
                        void* stream);
 
+/* Spectral filter (paper, Section 2.1, Prop. 1 and eq. 4, in the orthonormal form
+ * where the scale tables are folded into Q):
+ *   X' = Q_h^T (L o (Q_h X Q_w^T)) Q_w
+ * for a diagonal spectral operator given as an array L of rows x cols float32
+ * multipliers: L[k][l] scales 2D coefficient (k, l) (row k of the column transform,
+ * column l of the row transform).  L = 1 gives the round trip; the multipliers of a
+ * Neumann Poisson solve give the least-squares solver step of phase unwrapping.
+ * Fused like dct2d_roundtrip: each array is read once and written once, the multiply
+ * happens on chip between the forward and inverse transforms, float32 arithmetic on
+ * the vector ALU (the DCT2D_FP32 path, with the round trip's frozen kernel variant).
+ *   in, out, batch, rows, cols, in_stride, out_stride: as dct2d_transform_ex (in ==
+ *     out allowed; sizes as the basic calls).
+ *   lambda: device pointer to the multipliers, row-major with pitch cols, 4-byte
+ *     aligned; read only; must not overlap the output arrays.
+ *   lambda_stride: 0 = one operator shared by every array; otherwise >= rows*cols and
+ *     array b uses lambda + b*lambda_stride (one extra read of rows*cols floats per
+ *     array).
+ * Errors: as dct2d_transform_ex; DCT2D_ERR_STRIDE for a negative or too small
+ * lambda_stride, DCT2D_ERR_ARG for a null lambda (batch > 0) or lambda overlapping
+ * the output, DCT2D_ERR_ALIGN for a misaligned lambda. */
+int dct2d_filter(const float* in, float* out, int64_t batch, int32_t rows, int32_t cols,
+                 int64_t in_stride, int64_t out_stride, const float* lambda, int64_t lambda_stride,
+                 void* stream);
+
 /* ---- ragged batches: many arrays of different shapes in one launch ------------------
  * A descriptor names one array inside a caller buffer: its first element is at
  * base + offset (floats), its shape rows x cols (pitch = cols).  Arrays must not

@@ -23,7 +23,7 @@ PRECISIONS = {"fp32": FP32, "bf16x3": SPLIT_BF16X3, "bf16x6": SPLIT_BF16X6, "fp1
 DIRECTIONS = {"forward": FORWARD, "inverse": INVERSE, "roundtrip": ROUNDTRIP}
 
 EXPORTS = ("dct2d_init", "dct2d_finalize", "dct2d_forward", "dct2d_inverse", "dct2d_roundtrip",
-           "dct2d_transform_ex", "dct2d_ragged_plan_create", "dct2d_ragged_execute",
+           "dct2d_transform_ex", "dct2d_filter", "dct2d_ragged_plan_create", "dct2d_ragged_execute",
            "dct2d_ragged_plan_destroy", "dct2d_ragged_plan_info", "dct2d_variant_count",
            "dct2d_get_variant", "dct2d_set_variant", "dct2d_tune", "dct2d_status_string", "dct2d_version")
 
@@ -57,6 +57,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     for n in ("dct2d_forward", "dct2d_inverse", "dct2d_roundtrip"):
         getattr(lib, n).argtypes = [vp, i64, i32, i32, i64, vp]
     lib.dct2d_transform_ex.argtypes = [c_int, vp, vp, i64, i32, i32, i64, i64, c_int, vp]
+    lib.dct2d_filter.argtypes = [vp, vp, i64, i32, i32, i64, i64, vp, i64, vp]
     lib.dct2d_ragged_plan_create.argtypes = [ctypes.POINTER(Block), i64, c_int, c_int, ctypes.POINTER(vp)]
     lib.dct2d_ragged_execute.argtypes = [vp, vp, vp]
     lib.dct2d_ragged_plan_destroy.argtypes = [vp]
@@ -154,6 +155,31 @@ def transform(inp, out=None, direction="forward", precision="auto", stream=None)
     rc = load().dct2d_transform_ex(d, ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()), batch,
                                    rows, cols, stride, stride, p, ctypes.c_void_p(_stream(stream)))
     _check(rc, "dct2d_transform_ex")
+    return out
+
+
+def filter(inp, lam, out=None, stream=None):
+    """Spectral filter Q_h^T (lam o (Q_h X Q_w^T)) Q_w of every (rows, cols) array of inp
+    (dct2d_filter; Prop. 1, eq. 4).  lam: float32 CUDA tensor of shape (rows, cols), one
+    operator for all arrays, or inp's shape, one per array.  out may be inp (in place)."""
+    import torch
+    if out is None:
+        out = torch.empty_like(inp)
+    batch, rows, cols, stride = _geometry(inp, None, None, None)
+    if out.shape != inp.shape or not out.is_contiguous():
+        raise ValueError("out must be contiguous with the input's shape")
+    if lam.dtype != torch.float32 or not lam.is_cuda or not lam.is_contiguous():
+        raise TypeError("lam must be a contiguous float32 CUDA tensor")
+    if tuple(lam.shape) == (rows, cols):
+        lam_stride = 0
+    elif lam.shape == inp.shape:
+        lam_stride = rows * cols
+    else:
+        raise ValueError("lam must have shape (rows, cols) or the input's shape")
+    rc = load().dct2d_filter(ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()), batch, rows, cols,
+                             stride, stride, ctypes.c_void_p(lam.data_ptr()), lam_stride,
+                             ctypes.c_void_p(_stream(stream)))
+    _check(rc, "dct2d_filter")
     return out
 
 

@@ -179,6 +179,34 @@ int dct2d_transform_ex(int dir, const float* in, float* out, int64_t batch, int3
     return run(dir, in, out, batch, rows, cols, in_stride, out_stride, precision, stream);
 }
 
+int dct2d_filter(const float* in, float* out, int64_t batch, int32_t rows, int32_t cols, int64_t in_stride,
+                 int64_t out_stride, const float* lambda, int64_t lambda_stride, void* stream)
+{
+    int rc = validate(DCT2D_ROUNDTRIP, in, out, batch, rows, cols, in_stride, out_stride, DCT2D_FP32);
+    if (rc != DCT2D_OK) return rc;
+    const int64_t n = (int64_t)rows * cols;
+    if (lambda_stride < 0 || (lambda_stride > 0 && lambda_stride < n)) return DCT2D_ERR_STRIDE;
+    if (batch == 0) return DCT2D_OK;
+    if (!lambda) return DCT2D_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(lambda) & 3u) return DCT2D_ERR_ALIGN;
+    {
+        // the multipliers are read while the outputs are written: no overlap
+        const char* l0 = reinterpret_cast<const char*>(lambda);
+        const char* l1 = l0 + ((batch - 1) * lambda_stride + n) * 4;
+        const char* o0 = reinterpret_cast<const char*>(out);
+        const char* o1 = o0 + ((batch - 1) * out_stride + n) * 4;
+        if (l0 < o1 && o0 < l1) return DCT2D_ERR_ARG;
+    }
+    const DeviceTables* t = tables_current(&rc);
+    if (!t) return rc;
+    // the fused round trip's kernel configuration, with the multiply between the passes
+    Job j{DIR_FILTER, in, out, batch, rows, cols, in_stride, out_stride, static_cast<hipStream_t>(stream),
+          variant_for(rows, cols, DCT2D_ROUNDTRIP, DCT2D_FP32)};
+    j.lam = lambda;
+    j.lam_stride = lambda_stride;
+    return launch_fp32(t, j);
+}
+
 int dct2d_variant_count(int32_t rows, int32_t cols, int dir, int precision)
 {
     if (!basic_size_ok(rows, cols) || dir < 0 || dir > 2 || precision < 0 || precision >= DCT2D_AUTO) return 0;

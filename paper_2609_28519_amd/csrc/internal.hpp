@@ -88,6 +88,10 @@ struct Addr {
     const int64_t* out_idx; // nullptr: strided
     float* const* in_slot;  // nullptr: base = in
     float* const* out_slot; // nullptr: base = out
+    // spectral filter only: multipliers of array b at lam + b * lam_stride (0: shared)
+    const float* lam = nullptr;
+    int64_t lam_stride = 0;
+    __device__ __forceinline__ const gfloat* lam_for(int64_t b) const { return (const gfloat*)lam + b * lam_stride; }
     __device__ __forceinline__ const gfloat* src(int64_t b) const
     {
         const float* base = in_slot ? *(const gfloat* const DCT_GLOBAL*)in_slot : in;
@@ -117,9 +121,14 @@ struct Addr {
     }
 };
 
+// Internal direction of the fused spectral filter (Prop. 1, eq. 4): the round trip
+// with the coefficients multiplied by Addr::lam between the forward and inverse
+// column transforms.  Float32 path only.
+constexpr int DIR_FILTER = 3;
+
 // ---- kernel launchers (each returns a DCT2D_* status) ------------------------------
 struct Job {
-    int dir;           // DCT2D_FORWARD / INVERSE / ROUNDTRIP
+    int dir;           // DCT2D_FORWARD / INVERSE / ROUNDTRIP, or DIR_FILTER
     const float* in;
     float* out;
     int64_t batch;
@@ -132,7 +141,9 @@ struct Job {
     float* const* in_slot = nullptr;  // optional device-resident base pointers
     float* const* out_slot = nullptr;
     bool shared = false;              // launched beside other kernels (a ragged plan's branch)
-    Addr addr() const { return Addr{in, out, in_stride, out_stride, in_idx, out_idx, in_slot, out_slot}; }
+    const float* lam = nullptr;       // DIR_FILTER: multipliers (device), per-array stride
+    int64_t lam_stride = 0;
+    Addr addr() const { return Addr{in, out, in_stride, out_stride, in_idx, out_idx, in_slot, out_slot, lam, lam_stride}; }
 };
 
 // Resolves the precision (DCT2D_AUTO -> the frozen per-size choice) and the frozen

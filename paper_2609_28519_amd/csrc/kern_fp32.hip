@@ -20,6 +20,10 @@
 //   k_rows / k_cols (an axis of 256 in a rectangle): the row pass and the column pass
 //     are separate launches over HBM (a thread owns a whole row or column; column
 //     accesses are coalesced across the wavefront's consecutive columns).
+// The spectral filter (Prop. 1, eq. 4; internal direction DIR_FILTER) is the fused round
+// trip of every kernel with one extra step where a thread holds a column's forward
+// coefficients: each is multiplied by its entry of the multiplier array before the
+// inverse column transform.  The data still crosses HBM once each way.
 #include "dct1d.hpp"
 #include "internal.hpp"
 
@@ -67,6 +71,38 @@ __device__ __forceinline__ void apply1d(float (&v)[L], twptr tw)
         // forward's values live in scalar registers across both transforms
         asm volatile("" : "+s"(tw));
         dct3_ortho<L>(v, tw);
+    }
+}
+
+// Spectral filter of one column in registers: forward transform, coefficient k times
+// lam[k * pitch], inverse transform (Prop. 1, eq. 4, with the orthonormal Q).
+template <int L>
+__device__ __forceinline__ void filter1d(float (&v)[L], const gfloat* lam, int pitch, twptr tw)
+{
+    dct2_ortho<L>(v, tw);
+#pragma unroll
+    for (int k = 0; k < L; ++k) v[k] *= lam[k * pitch];
+    asm volatile("" : "+s"(tw));
+    dct3_ortho<L>(v, tw);
+}
+
+// Filter step of the split kernels: o[k] *= lam[k * PITCH + off] for k < N, lam wave-uniform.
+// Every o[k] is final before the first multiplier load (the loads' offsets depend on a value
+// the empty asm statements order after the transform), and at most C loads are in flight:
+// loads scheduled into the tail of the transform find its temporaries live and, at the
+// register limit, go out one at a time with a wait after each.  32-bit byte offsets from the
+// uniform base keep each address in one register.
+template <int N, int PITCH, int C>
+__device__ __forceinline__ void scale_coefs(float (&o)[N], const gfloat* lam, int off)
+{
+#pragma unroll
+    for (int k = 0; k < N; ++k) asm volatile("" : "+v"(o[k]));
+    asm volatile("" : "+v"(off));
+    const DCT_GLOBAL char* lb = reinterpret_cast<const DCT_GLOBAL char*>(lam);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        o[k] *= *reinterpret_cast<const gfloat*>(lb + (uint32_t)((k * PITCH + off) * 4));
+        if (k % C == C - 1) asm volatile("" : "+v"(off) : "v"(o[k]));
     }
 }
 
@@ -123,12 +159,15 @@ k_fused(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* 
             float* col = lds + tb * C::BS + tl;
 #pragma unroll
             for (int r = 0; r < H; ++r) v[r] = col[r * C::P];
-            apply1d<H, DIR>(v, twh);
+            if constexpr (DIR == DIR_FILTER)
+                filter1d<H>(v, a.lam_for(b0 + tb < batch ? b0 + tb : b0) + tl, W, twh);
+            else
+                apply1d<H, DIR>(v, twh);
 #pragma unroll
             for (int r = 0; r < H; ++r) col[r * C::P] = v[r];
         }
         __syncthreads();
-        if (DIR == DCT2D_ROUNDTRIP) {
+        if (DIR >= DCT2D_ROUNDTRIP) {
             lds_row_pass<H, W, true>(lds, tb, tl, tww);
             __syncthreads();
         }
@@ -318,8 +357,11 @@ k_wave(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* _
             float c[H];
 #pragma unroll
             for (int r = 0; r < H; ++r) c[r] = tile_lds[C::at(r, tl)];
-            apply1d<H, DIR>(c, twh);
-            if (STAGE || DIR == DCT2D_ROUNDTRIP) {
+            if constexpr (DIR == DIR_FILTER)
+                filter1d<H>(c, a.lam_for(valid ? b : b0) + tl, W, twh);
+            else
+                apply1d<H, DIR>(c, twh);
+            if (STAGE || DIR >= DCT2D_ROUNDTRIP) {
 #pragma unroll
                 for (int r = 0; r < H; ++r) tile_lds[C::at(r, tl)] = c[r];
             } else if (valid) {
@@ -328,7 +370,7 @@ k_wave(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* _
                 for (int r = 0; r < H; ++r) dst[(int64_t)r * W] = c[r];
             }
         }
-        if (DIR == DCT2D_ROUNDTRIP) {
+        if (DIR >= DCT2D_ROUNDTRIP) {
             __syncthreads();
             tww = per_iteration(tww_in);
             if (tl < H) {
@@ -440,6 +482,31 @@ __device__ __forceinline__ void s128_array(const Addr& a, int64_t blk, float* T,
             for (int k = 0; k < H; ++k) dst[(int64_t)(2 * k + role) * L + idx] = o[k];
             __syncthreads(); // LDS reuse by the next array
             return;
+        }
+        if (DIR == DIR_FILTER) {
+            // The coefficients pass through the tile (coefficient row 2k + role of column idx
+            // at T[(2k + role) P + idx]), where lane t scales element t % 128 of rows 2i + t / 128
+            // with all of its 64 multiplier loads in flight at once: loaded beside the live
+            // coefficients, the same loads would go out one or two at a time.
+            // the loads go out once the transform is done (their offsets depend on a value
+            // the empty asm statements order after it) and fly during the barrier wait
+#pragma unroll
+            for (int k = 0; k < H; ++k) asm volatile("" : "+v"(o[k]));
+            int lt = t;
+            asm volatile("" : "+v"(lt));
+            const DCT_GLOBAL char* lb = reinterpret_cast<const DCT_GLOBAL char*>(uniform_ptr(a.lam_for(blk)));
+            float lq[H];
+#pragma unroll
+            for (int i = 0; i < H; ++i) lq[i] = *reinterpret_cast<const gfloat*>(lb + (uint32_t)((i * 256 + lt) * 4));
+            __syncthreads(); // every column read before the coefficients overwrite the tile
+#pragma unroll
+            for (int k = 0; k < H; ++k) T[(2 * k + role) * P + idx] = o[k];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < H; ++i) T[(2 * i + (t >> 7)) * P + idx] *= lq[i];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < H; ++k) o[k] = T[(2 * k + role) * P + idx];
         }
         // round trip: inverse columns on the same data (even -> DCT-III_64, odd -> DCT-IV_64)
         asm volatile("" : "+s"(tw));
@@ -595,14 +662,16 @@ __device__ __forceinline__ void split64_array(const Addr& a, int64_t b, float* T
                 for (int n = 0; n < H; ++n) v[n] = ROLE == 0 ? x[n] + x[N - 1 - n] : x[n] - x[N - 1 - n];
             }
             if constexpr (ROLE == 0) dct2_rec<N, H>(v, y, tw); else dct4_scaled<N, H>(v, y, tw);
-            if (DIR == DCT2D_ROUNDTRIP) {
+            if (DIR >= DCT2D_ROUNDTRIP) {
+                if (DIR == DIR_FILTER) // coefficient row 2k + ROLE of logical column lc
+                    scale_coefs<H, 2 * N, 32>(y, uniform_ptr(a.lam_for(b)), ROLE * N + (l < H ? 2 * l : 2 * (l - H) + 1));
                 tw_fence(tw);
                 // p (role 0: DCT-III_32 of the even coefficients) or q (role 1: DCT-IV_32 of the odd)
                 if constexpr (ROLE == 0) dct3_rec<N, H>(y, v, tw); else dct4_scaled<N, H>(y, v, tw);
             }
             __syncthreads(); // every column is read before the halves overwrite it
 #pragma unroll
-            for (int n = 0; n < H; ++n) T[C::at(H * ROLE + n, l)] = DIR == DCT2D_ROUNDTRIP ? v[n] : y[n];
+            for (int n = 0; n < H; ++n) T[C::at(H * ROLE + n, l)] = DIR >= DCT2D_ROUNDTRIP ? v[n] : y[n];
             __syncthreads();
         } else {
             // ---- inverse columns: logical column l; role 0 inverts the even coefficient
@@ -958,6 +1027,14 @@ __device__ __forceinline__ void col_inv(const float (&o)[H], float (&R)[H], twpt
     settle(R);
 }
 
+// Filter: coefficient row 2k + CR of array column 2 cc + G times its multiplier.
+template <int G, int CR>
+__device__ __forceinline__ void scale_col(float (&o)[H], const gfloat* lam, int wid)
+{
+    scale_coefs<H, 2 * L, 32>(o, lam, CR * L + 2 * (lane_t(wid) & 127) + G);
+    settle(o);
+}
+
 // Column halves into the tile: rows 0..127 hold a, rows 128..255 hold b (column cc).
 template <int CR>
 __device__ __forceinline__ void put_halves(float* T, int wid, const float (&R)[H])
@@ -1050,7 +1127,7 @@ __device__ __forceinline__ void rows_out(gfloat* dst, float* T, int wid, const f
 
 // One (group, column half) path of one array.
 template <int DIR, int G, int CR>
-__device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, int wid, twptr tw)
+__device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, int wid, twptr tw, const gfloat* lam)
 {
     float R[H];
     if constexpr (DIR == DCT2D_FORWARD) {
@@ -1098,6 +1175,7 @@ __device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, i
                 {
                     float o[H];
                     col_fwd<CR>(T, wid, o, tw);
+                    if constexpr (DIR == DIR_FILTER) scale_col<G, CR>(o, lam, wid);
                     tw_fence(tw);
                     col_inv<CR>(o, R, tw);
                 }
@@ -1113,6 +1191,7 @@ __device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, i
                 {
                     float o[H];
                     col_fwd<CR>(T, wid, o, tw);
+                    if constexpr (DIR == DIR_FILTER) scale_col<G, CR>(o, lam, wid);
                     tw_fence(tw);
                     col_inv<CR>(o, R, tw);
                 }
@@ -1149,12 +1228,13 @@ k_split256(Addr a, int64_t batch, const float2* __restrict__ tw_in, int stagger)
         const twptr tw = per_iteration(tw_in);
         const gfloat* src = uniform_ptr(a.src(blk));
         gfloat* dst = uniform_ptr(a.dst(blk));
+        const gfloat* lam = DIR == DIR_FILTER ? uniform_ptr(a.lam_for(blk)) : nullptr;
         if (g == 0) {
-            if (cr == 0) path<DIR, 0, 0>(src, dst, T, wid, tw);
-            else path<DIR, 0, 1>(src, dst, T, wid, tw);
+            if (cr == 0) path<DIR, 0, 0>(src, dst, T, wid, tw, lam);
+            else path<DIR, 0, 1>(src, dst, T, wid, tw, lam);
         } else {
-            if (cr == 0) path<DIR, 1, 0>(src, dst, T, wid, tw);
-            else path<DIR, 1, 1>(src, dst, T, wid, tw);
+            if (cr == 0) path<DIR, 1, 0>(src, dst, T, wid, tw, lam);
+            else path<DIR, 1, 1>(src, dst, T, wid, tw, lam);
         }
     }
 }
@@ -1199,7 +1279,10 @@ k_cols(Addr a, int64_t batch, int32_t cols, const float2* __restrict__ tw_in)
     float v[L];
 #pragma unroll
     for (int r = 0; r < L; ++r) v[r] = src[(int64_t)r * cols];
-    apply1d<L, DIR>(v, tw);
+    if constexpr (DIR == DIR_FILTER)
+        filter1d<L>(v, a.lam_for(b) + c, cols, tw);
+    else
+        apply1d<L, DIR>(v, tw);
 #pragma unroll
     for (int r = 0; r < L; ++r) dst[(int64_t)r * cols] = v[r];
 }
@@ -1220,6 +1303,9 @@ int launch_fused_hw(const DeviceTables* t, const Job& j)
     case DCT2D_INVERSE:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused<H, W, DCT2D_INVERSE>, C::NT, 0);
         break;
+    case DIR_FILTER:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused<H, W, DIR_FILTER>, C::NT, 0);
+        break;
     default:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fused<H, W, DCT2D_ROUNDTRIP>, C::NT, 0);
         break;
@@ -1233,6 +1319,9 @@ int launch_fused_hw(const DeviceTables* t, const Job& j)
         break;
     case DCT2D_INVERSE:
         k_fused<H, W, DCT2D_INVERSE><<<grid, C::NT, 0, j.stream>>>(j.addr(), j.batch, twh, tww);
+        break;
+    case DIR_FILTER:
+        k_fused<H, W, DIR_FILTER><<<grid, C::NT, 0, j.stream>>>(j.addr(), j.batch, twh, tww);
         break;
     default:
         k_fused<H, W, DCT2D_ROUNDTRIP><<<grid, C::NT, 0, j.stream>>>(j.addr(), j.batch, twh, tww);
@@ -1279,6 +1368,7 @@ int launch_wave_stage(const DeviceTables* t, const Job& j)
     switch (j.dir) {
     case DCT2D_FORWARD: return launch_wave_dir<H, W, DCT2D_FORWARD, STAGE>(t, j);
     case DCT2D_INVERSE: return launch_wave_dir<H, W, DCT2D_INVERSE, STAGE>(t, j);
+    case DIR_FILTER: return launch_wave_dir<H, W, DIR_FILTER, STAGE>(t, j);
     default: return launch_wave_dir<H, W, DCT2D_ROUNDTRIP, STAGE>(t, j);
     }
 }
@@ -1335,6 +1425,8 @@ int launch_split128(const DeviceTables* t, const Job& j, bool stage)
         return stage ? launch_split128_dir<DCT2D_FORWARD, true>(t, j) : launch_split128_dir<DCT2D_FORWARD, false>(t, j);
     case DCT2D_INVERSE:
         return stage ? launch_split128_dir<DCT2D_INVERSE, true>(t, j) : launch_split128_dir<DCT2D_INVERSE, false>(t, j);
+    case DIR_FILTER:
+        return stage ? launch_split128_dir<DIR_FILTER, true>(t, j) : launch_split128_dir<DIR_FILTER, false>(t, j);
     default:
         return stage ? launch_split128_dir<DCT2D_ROUNDTRIP, true>(t, j)
                      : launch_split128_dir<DCT2D_ROUNDTRIP, false>(t, j);
@@ -1359,6 +1451,7 @@ int launch_split64(const DeviceTables* t, const Job& j)
     switch (j.dir) {
     case DCT2D_FORWARD: return launch_split64_dir<DCT2D_FORWARD>(t, j);
     case DCT2D_INVERSE: return launch_split64_dir<DCT2D_INVERSE>(t, j);
+    case DIR_FILTER: return launch_split64_dir<DIR_FILTER>(t, j);
     default: return launch_split64_dir<DCT2D_ROUNDTRIP>(t, j);
     }
 }
@@ -1383,6 +1476,7 @@ int launch_split256(const DeviceTables* t, const Job& j)
     switch (j.dir) {
     case DCT2D_FORWARD: return launch_split256_dir<DCT2D_FORWARD>(t, j);
     case DCT2D_INVERSE: return launch_split256_dir<DCT2D_INVERSE>(t, j);
+    case DIR_FILTER: return launch_split256_dir<DIR_FILTER>(t, j);
     default: return launch_split256_dir<DCT2D_ROUNDTRIP>(t, j);
     }
 }
@@ -1438,7 +1532,8 @@ int cols_any(const DeviceTables* t, int len, const Addr& a, int64_t batch, int c
 int launch_two_pass(const DeviceTables* t, const Job& j)
 {
     const Addr first = j.addr();
-    const Addr inplace{j.out, j.out, j.out_stride, j.out_stride, j.out_idx, j.out_idx, j.out_slot, j.out_slot};
+    const Addr inplace{j.out, j.out, j.out_stride, j.out_stride, j.out_idx, j.out_idx, j.out_slot, j.out_slot,
+                       j.lam, j.lam_stride};
     int rc;
     switch (j.dir) {
     case DCT2D_FORWARD:
@@ -1452,7 +1547,8 @@ int launch_two_pass(const DeviceTables* t, const Job& j)
     default:
         rc = rows_any<DCT2D_FORWARD>(t, j.cols, first, j.batch, j.rows, j.stream);
         if (rc) return rc;
-        rc = cols_any<DCT2D_ROUNDTRIP>(t, j.rows, inplace, j.batch, j.cols, j.stream);
+        rc = j.dir == DIR_FILTER ? cols_any<DIR_FILTER>(t, j.rows, inplace, j.batch, j.cols, j.stream)
+                                 : cols_any<DCT2D_ROUNDTRIP>(t, j.rows, inplace, j.batch, j.cols, j.stream);
         if (rc) return rc;
         return rows_any<DCT2D_INVERSE>(t, j.cols, inplace, j.batch, j.rows, j.stream);
     }

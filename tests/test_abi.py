@@ -57,3 +57,17 @@ def test_argument_validation_on_host():
     assert lib.dct2d_variant_count(26, 8, 0, 0) == 0
     assert lib.dct2d_get_variant(26, 8, 0, 0) == -2
     assert lib.dct2d_set_variant(8, 8, 0, 0, 99) == -1
+
+
+def test_filter_validation_on_host():
+    """dct2d_filter rejects bad arguments before any device work (fake device addresses)."""
+    lib = dct.load()
+    a = ctypes.c_void_p(0x100000)
+    assert lib.dct2d_filter(None, None, 0, 8, 8, 64, 64, None, 0, None) == 0             # batch 0: no-op
+    assert lib.dct2d_filter(None, None, 0, 26, 8, 208, 208, None, 0, None) == -2         # size
+    assert lib.dct2d_filter(None, None, 0, 8, 8, 64, 64, None, -1, None) == -3           # lambda_stride < 0
+    assert lib.dct2d_filter(None, None, 0, 8, 8, 64, 64, None, 10, None) == -3           # 0 < stride < 64
+    assert lib.dct2d_filter(a, a, 3, 8, 8, 64, 64, None, 0, None) == -1                  # null lambda
+    assert lib.dct2d_filter(a, a, 3, 8, 8, 64, 64, ctypes.c_void_p(0x200002), 0, None) == -4  # misaligned
+    assert lib.dct2d_filter(a, a, 3, 8, 8, 64, 64, ctypes.c_void_p(0x100100), 0, None) == -1  # overlaps out
+    assert lib.dct2d_filter(a, a, -1, 8, 8, 64, 64, ctypes.c_void_p(0x200000), 0, None) == -1  # batch < 0

@@ -1,0 +1,167 @@
+"""GPU parity of the fused spectral filter (dct2d_filter) against the FP64 oracle.
+
+The filter is X' = Q_h^T (L o (Q_h X Q_w^T)) Q_w (Prop. 1, eq. 4, orthonormal form).
+Metric: e = ||X'_gpu - X'_oracle||_F / (max|L| ||X||_F) per array, gate 4e-6.  The
+bound follows from the round trip's: the forward part is within the forward gate of
+||X||, the multiply scales that error by at most max|L| and adds one float32
+rounding, and the inverse adds at most the inverse gate of ||L o Y|| <= max|L| ||X||;
+so the error stays within max|L| times the round-trip gate.  The oracle receives the
+float32 multipliers the kernel reads, promoted exactly to double.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_util import to_gpu
+
+pytestmark = pytest.mark.gpu
+GATE = 4e-6
+SQUARES = ((8, 8), (16, 16), (32, 32), (64, 64), (128, 128), (256, 256))
+RECTS = ((8, 16), (16, 8), (32, 64), (64, 32), (8, 64), (64, 8), (128, 64), (16, 128), (256, 32), (8, 256))
+
+
+def _lib():
+    import paper_2609_28519_amd as dct
+    dct.init(0)
+    return dct
+
+
+def _batch(h, w):
+    m = max(h, w)
+    return 5 if m == 256 else 11 if m == 128 else 4096 // m + 3  # several tiles and a ragged tail
+
+
+def poisson_multipliers(h, w):
+    """1 / (2 cos(pi k / h) + 2 cos(pi l / w) - 4), 0 at (0, 0): the Neumann Poisson solve."""
+    k = np.arange(h)[:, None]
+    l = np.arange(w)[None, :]
+    mu = 2.0 * np.cos(np.pi * k / h) + 2.0 * np.cos(np.pi * l / w) - 4.0
+    lam = np.zeros((h, w))
+    lam[mu != 0] = 1.0 / mu[mu != 0]
+    return lam.astype(np.float32)
+
+
+def _score(x, y, lam):
+    ref = oracle.filter(x, lam.astype(np.float64))
+    lm = np.abs(lam.astype(np.float64))
+    lmax = lm.max() if lam.ndim == 2 else lm.reshape(lam.shape[0], -1).max(axis=1)
+    num = np.sqrt(((y.astype(np.float64) - ref) ** 2).sum(axis=(1, 2)))
+    den = np.sqrt((x.astype(np.float64) ** 2).sum(axis=(1, 2))) * lmax
+    return num / np.where(den > 0, den, 1.0)
+
+
+def _filter(x, lam, inplace=True):
+    import torch
+    dct = _lib()
+    t = to_gpu(x)
+    lt = to_gpu(lam)
+    out = dct.filter(t, lt, out=t if inplace else None)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), t.cpu().numpy()
+
+
+@pytest.mark.parametrize("h,w", SQUARES + RECTS)
+@pytest.mark.parametrize("shared", [True, False])
+def test_filter_random_multipliers(h, w, shared):
+    g = np.random.default_rng(11 * h + w + shared)
+    b = _batch(h, w)
+    x = g.standard_normal((b, h, w)).astype(np.float32)
+    lam = g.uniform(-2.0, 2.0, (h, w) if shared else (b, h, w)).astype(np.float32)
+    y, t = _filter(x, lam, inplace=shared)
+    if not shared:
+        assert np.array_equal(t, x), "out-of-place call modified its input"
+    e = _score(x, y, lam)
+    assert np.isfinite(e).all() and e.max() <= GATE, "%dx%d shared=%s: %.3e at %d" % (h, w, shared, e.max(),
+                                                                                     int(np.argmax(e)))
+
+
+@pytest.mark.parametrize("h,w", SQUARES + ((8, 32), (64, 16), (256, 32)))
+def test_filter_poisson_solve(h, w):
+    """The least-squares (Neumann Poisson) step of phase unwrapping: large multipliers."""
+    g = np.random.default_rng(5 * h + w)
+    x = g.standard_normal((_batch(h, w), h, w)).astype(np.float32)
+    lam = poisson_multipliers(h, w)
+    y, _ = _filter(x, lam)
+    e = _score(x, y, lam)
+    assert np.isfinite(e).all() and e.max() <= GATE, "%dx%d: %.3e" % (h, w, e.max())
+
+
+@pytest.mark.parametrize("h,w", SQUARES + ((8, 64), (128, 32), (8, 256)))
+def test_unit_multipliers_reproduce_the_round_trip_bitwise(h, w):
+    """L = 1: multiplying by 1.0f is exact, so the filter equals the fused round trip of the
+    same kernel configuration bit for bit."""
+    import torch
+    dct = _lib()
+    g = np.random.default_rng(h * w)
+    x = g.standard_normal((_batch(h, w), h, w)).astype(np.float32)
+    t = to_gpu(x)
+    rt = dct.transform(t, None, "roundtrip", "fp32")
+    f = dct.filter(t, to_gpu(np.ones((h, w), np.float32)))
+    torch.cuda.synchronize()
+    assert np.array_equal(rt.cpu().numpy(), f.cpu().numpy())
+
+
+@pytest.mark.parametrize("h,w", ((8, 8), (64, 64), (128, 128), (256, 256), (16, 128)))
+def test_zero_multipliers_and_zero_blocks(h, w):
+    g = np.random.default_rng(3)
+    x = g.standard_normal((3, h, w)).astype(np.float32)
+    y, _ = _filter(x, np.zeros((h, w), np.float32))
+    assert np.all(y == 0.0)
+    x[1] = 0.0
+    y, _ = _filter(x, g.uniform(-1, 1, (h, w)).astype(np.float32))
+    assert np.all(y[1] == 0.0)
+
+
+@pytest.mark.parametrize("h,w", ((8, 8), (32, 32), (64, 64), (128, 128), (256, 256), (8, 64)))
+def test_filter_every_round_trip_variant(h, w):
+    """The filter runs on the round trip's frozen kernel variant; every variant the autotuner
+    may freeze must carry the multiply."""
+    dct = _lib()
+    g = np.random.default_rng(h + w)
+    x = g.standard_normal((_batch(h, w), h, w)).astype(np.float32)
+    lam = g.uniform(-2.0, 2.0, (x.shape[0], h, w)).astype(np.float32)
+    keep = dct.get_variant(h, w, "roundtrip", "fp32")
+    try:
+        for v in range(dct.variant_count(h, w, "roundtrip", "fp32")):
+            dct.set_variant(h, w, "roundtrip", "fp32", v)
+            y, _ = _filter(x, lam)
+            e = _score(x, y, lam)
+            assert np.isfinite(e).all() and e.max() <= GATE, "%dx%d v%d: %.3e" % (h, w, v, e.max())
+    finally:
+        dct.set_variant(h, w, "roundtrip", "fp32", keep)
+
+
+def test_batch_zero_and_argument_errors():
+    import torch
+    dct = _lib()
+    t = torch.zeros((0, 8, 8), device="cuda")
+    assert dct.filter(t, torch.ones((8, 8), device="cuda")).shape == (0, 8, 8)
+    x = torch.zeros((2, 8, 8), device="cuda")
+    with pytest.raises(ValueError):
+        dct.filter(x, torch.ones((8, 16), device="cuda"))
+    with pytest.raises(dct.DCT2DError):
+        dct.filter(x, x, out=x)  # the per-array multipliers would overlap the in-place output
+
+
+@pytest.mark.parametrize("n", (8, 16, 32, 64, 128, 256))
+def test_filter_full_size_sampled(n):
+    """512 MiB batch (2^27/N^2 arrays of N(0,1)), in place, one shared Poisson operator, as the
+    benchmark times it; 96 sampled arrays (first, last, random) checked against the oracle."""
+    import torch
+    import workloads
+    dct = _lib()
+    bt = workloads.c3_normal(n)
+    batch = bt.x.shape[0]
+    g = np.random.default_rng(n + 1)
+    idx = np.unique(np.concatenate([[0, batch - 1], g.integers(0, batch, 94)]))
+    xs = bt.x[idx].copy()
+    t = to_gpu(bt.x)
+    del bt
+    lam = poisson_multipliers(n, n)
+    dct.filter(t, to_gpu(lam), out=t)
+    torch.cuda.synchronize()
+    y = t[torch.from_numpy(idx).cuda()].cpu().numpy()
+    del t
+    torch.cuda.empty_cache()
+    e = _score(xs, y, lam)
+    assert np.isfinite(e).all() and e.max() <= GATE, "N=%d: %.3e" % (n, e.max())
