@@ -351,16 +351,29 @@ k_wave(Addr a, int64_t batch, const float2* __restrict__ twh_in, const float2* _
             if (DIR == DCT2D_INVERSE) dct3_ortho<W>(v, tww); else dct2_ortho<W>(v, tww);
             lds_row_out<H, W>(tile_lds, tl, v);
         }
+        // filter: the multipliers of column tl are requested here, so they arrive during the
+        // column reads and the forward transform instead of stalling the multiply
+        float lq[H];
+        if (DIR == DIR_FILTER && tl < W) {
+            const gfloat* lp = a.lam_for(valid ? b : b0) + tl;
+#pragma unroll
+            for (int r = 0; r < H; ++r) lq[r] = lp[r * W];
+        }
         __syncthreads();
         twptr twh = per_iteration(twh_in); // the column pass re-reads its twiddles (see per_iteration)
         if (tl < W) {
             float c[H];
 #pragma unroll
             for (int r = 0; r < H; ++r) c[r] = tile_lds[C::at(r, tl)];
-            if constexpr (DIR == DIR_FILTER)
-                filter1d<H>(c, a.lam_for(valid ? b : b0) + tl, W, twh);
-            else
+            if constexpr (DIR == DIR_FILTER) {
+                dct2_ortho<H>(c, twh);
+#pragma unroll
+                for (int r = 0; r < H; ++r) c[r] *= lq[r];
+                asm volatile("" : "+s"(twh));
+                dct3_ortho<H>(c, twh);
+            } else {
                 apply1d<H, DIR>(c, twh);
+            }
             if (STAGE || DIR >= DCT2D_ROUNDTRIP) {
 #pragma unroll
                 for (int r = 0; r < H; ++r) tile_lds[C::at(r, tl)] = c[r];
