@@ -165,3 +165,38 @@ def test_filter_full_size_sampled(n):
     torch.cuda.empty_cache()
     e = _score(xs, y, lam)
     assert np.isfinite(e).all() and e.max() <= GATE, "N=%d: %.3e" % (n, e.max())
+
+
+@pytest.mark.parametrize("h,w", ((8, 8), (32, 16), (64, 64), (128, 128), (256, 256), (8, 256)))
+def test_filter_strided_through_the_c_abi(h, w):
+    """dct2d_filter called directly with padded strides: in_stride, out_stride and
+    lambda_stride all above rows*cols; the padding between arrays is left untouched."""
+    import ctypes
+    import torch
+    dct = _lib()
+    n = h * w
+    batch = 7
+    si, so, sl = n + 8, n + 12, n + 4
+    g = np.random.default_rng(h * 3 + w)
+    x = g.standard_normal((batch, h, w)).astype(np.float32)
+    lam = g.uniform(-2.0, 2.0, (batch, h, w)).astype(np.float32)
+    fill = np.float32(1234.5)
+    bi = np.full(batch * si, fill, np.float32)
+    bl = np.full(batch * sl, fill, np.float32)
+    for b in range(batch):
+        bi[b * si:b * si + n] = x[b].ravel()
+        bl[b * sl:b * sl + n] = lam[b].ravel()
+    ti, tl = to_gpu(bi), to_gpu(bl)
+    to = torch.full((batch * so,), float(fill), device="cuda")
+    rc = dct.load().dct2d_filter(ctypes.c_void_p(ti.data_ptr()), ctypes.c_void_p(to.data_ptr()), batch, h, w, si, so,
+                                 ctypes.c_void_p(tl.data_ptr()), sl,
+                                 ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 0, dct.status_string(rc)
+    torch.cuda.synchronize()
+    out = to.cpu().numpy()
+    y = np.stack([out[b * so:b * so + n].reshape(h, w) for b in range(batch)])
+    for b in range(batch):
+        assert np.all(out[b * so + n:(b + 1) * so] == fill)
+    assert np.array_equal(ti.cpu().numpy(), bi)
+    e = _score(x, y, lam)
+    assert np.isfinite(e).all() and e.max() <= GATE, "%dx%d: %.3e" % (h, w, e.max())
