@@ -88,6 +88,8 @@ def main():
             for d in DIRS:
                 # tunes the variants of every float32-accurate path, freezes the fastest path for "auto"
                 dct.tune(n, n, d, "auto", batch=(1 << args.log2_floats) // (n * n), stream=stream)
+            if not args.no_filter:
+                dct.tune(n, n, "filter", "fp32", batch=(1 << args.log2_floats) // (n * n), stream=stream)
         torch.cuda.synchronize()
     if args.save_policy:
         dct.save_policy(args.save_policy)
@@ -96,6 +98,7 @@ def main():
             path = dct.get_variant(n, n, d, "auto")
             name = {v: k for k, v in dct.PRECISIONS.items()}[path]
             tuned["%d/%s" % (n, d)] = "%s/v%d" % (name, dct.get_variant(n, n, d, name))
+        tuned["%d/filter" % n] = "fp32/v%d" % dct.get_variant(n, n, "filter", "fp32")
 
     def call(n, d, prec, t):
         return dct.transform(t, t, d, prec, stream=stream)

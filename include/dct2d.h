@@ -71,6 +71,8 @@ extern "C" {
 #define DCT2D_FORWARD   0   /* Y = Q_h X Q_w^T            (eq. 2)                  */
 #define DCT2D_INVERSE   1   /* X = Q_h^T Y Q_w            (eq. 2)                  */
 #define DCT2D_ROUNDTRIP 2   /* inverse(forward(X)), fused (Section 3.1, Prop. 1)   */
+#define DCT2D_FILTER    3   /* spectral filter (dct2d_filter, Prop. 1, eq. 4): accepted
+                               by the policy / autotuner calls only, float32 path    */
 
 /* ---- arithmetic paths ------------------------------------------------------------
  * DCT2D_FP32        float32 fast transforms on the vector ALU (all sizes).
@@ -199,7 +201,10 @@ int dct2d_ragged_plan_info(const dct2d_ragged_plan* plan, int64_t* items, int32_
  * candidate variants for one case on scratch data it allocates itself (call it
  * outside timed regions) and freezes the fastest one that passes the library's own
  * self-consistency check; dct2d_get_variant / dct2d_set_variant read and override the
- * frozen table; dct2d_variant_count gives the number of candidates (0 = none). */
+ * frozen table; dct2d_variant_count gives the number of candidates (0 = none).
+ * `dir` may also be DCT2D_FILTER, with precision DCT2D_FP32 (or DCT2D_AUTO, which for the
+ * filter always means DCT2D_FP32): the filter's own frozen variant, which starts as the
+ * round trip's and is tuned on scratch data with one shared multiplier array. */
 int dct2d_variant_count(int32_t rows, int32_t cols, int dir, int precision);
 int dct2d_get_variant(int32_t rows, int32_t cols, int dir, int precision);
 int dct2d_set_variant(int32_t rows, int32_t cols, int dir, int precision, int variant);

@@ -16,11 +16,13 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libdct2d.so")
 
-FORWARD, INVERSE, ROUNDTRIP = 0, 1, 2
+FORWARD, INVERSE, ROUNDTRIP, FILTER = 0, 1, 2, 3
 FP32, SPLIT_BF16X3, SPLIT_BF16X6, SPLIT_FP16X3, BF16, FP16, FP8_E4M3, AUTO = range(8)
 PRECISIONS = {"fp32": FP32, "bf16x3": SPLIT_BF16X3, "bf16x6": SPLIT_BF16X6, "fp16x3": SPLIT_FP16X3,
               "bf16": BF16, "fp16": FP16, "fp8": FP8_E4M3, "auto": AUTO}
-DIRECTIONS = {"forward": FORWARD, "inverse": INVERSE, "roundtrip": ROUNDTRIP}
+# "filter" names the spectral filter's entry of the policy / autotuner (dct2d_filter); the
+# transform calls accept the first three only
+DIRECTIONS = {"forward": FORWARD, "inverse": INVERSE, "roundtrip": ROUNDTRIP, "filter": FILTER}
 
 EXPORTS = ("dct2d_init", "dct2d_finalize", "dct2d_forward", "dct2d_inverse", "dct2d_roundtrip",
            "dct2d_transform_ex", "dct2d_filter", "dct2d_ragged_plan_create", "dct2d_ragged_execute",

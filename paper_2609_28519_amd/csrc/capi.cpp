@@ -19,10 +19,12 @@ namespace {
 
 constexpr int kNumPrec = 8;
 
-// Frozen variant table: index [log2 rows - 3][log2 cols - 3][dir][precision]; starts from the
-// per-size defaults (the variants measured fastest on MI355X), overridable by the tuner.
+// Frozen variant table: index [log2 rows - 3][log2 cols - 3][dir][precision] (dir 3: the
+// spectral filter, float32 only); starts from the per-size defaults (the variants measured
+// fastest on MI355X; the filter starts from the round trip's), overridable by the tuner.
+constexpr int kNumDir = 4;
 std::mutex g_policy_mu;
-int g_variant[6][6][3][kNumPrec];
+int g_variant[6][6][kNumDir][kNumPrec];
 bool g_policy_ready = false;
 
 void policy_init_locked()
@@ -30,9 +32,10 @@ void policy_init_locked()
     if (g_policy_ready) return;
     for (int r = 0; r < 6; ++r)
         for (int c = 0; c < 6; ++c)
-            for (int d = 0; d < 3; ++d)
+            for (int d = 0; d < kNumDir; ++d)
                 for (int p = 0; p < kNumPrec; ++p)
-                    g_variant[r][c][d][p] = p == DCT2D_FP32 ? fp32_default_variant(8 << r, 8 << c, d) : 0;
+                    g_variant[r][c][d][p] =
+                        p == DCT2D_FP32 ? fp32_default_variant(8 << r, 8 << c, d == DIR_FILTER ? DCT2D_ROUNDTRIP : d) : 0;
     g_policy_ready = true;
 }
 
@@ -113,6 +116,7 @@ int run(int dir, const float* in, float* out, int64_t batch, int32_t rows, int32
 int variant_count(int rows, int cols, int dir, int prec)
 {
     if (prec == DCT2D_FP32) return fp32_variant_count(rows, cols, dir);
+    if (dir == DIR_FILTER) return 0; // the filter exists on the float32 path only
     if (!mfma_supported(rows, cols, prec)) return 0;
     return mfma_variant_count(rows, cols, dir, prec);
 }
@@ -199,9 +203,10 @@ int dct2d_filter(const float* in, float* out, int64_t batch, int32_t rows, int32
     }
     const DeviceTables* t = tables_current(&rc);
     if (!t) return rc;
-    // the fused round trip's kernel configuration, with the multiply between the passes
+    // a fused round-trip kernel with the multiply between the passes, in the filter's own
+    // frozen variant
     Job j{DIR_FILTER, in, out, batch, rows, cols, in_stride, out_stride, static_cast<hipStream_t>(stream),
-          variant_for(rows, cols, DCT2D_ROUNDTRIP, DCT2D_FP32)};
+          variant_for(rows, cols, DIR_FILTER, DCT2D_FP32)};
     j.lam = lambda;
     j.lam_stride = lambda_stride;
     return launch_fp32(t, j);
@@ -209,23 +214,29 @@ int dct2d_filter(const float* in, float* out, int64_t batch, int32_t rows, int32
 
 int dct2d_variant_count(int32_t rows, int32_t cols, int dir, int precision)
 {
-    if (!basic_size_ok(rows, cols) || dir < 0 || dir > 2 || precision < 0 || precision >= DCT2D_AUTO) return 0;
+    if (!basic_size_ok(rows, cols) || dir < 0 || dir > DCT2D_FILTER || precision < 0 || precision >= DCT2D_AUTO)
+        return 0;
     return variant_count(rows, cols, dir, precision);
 }
 
 int dct2d_get_variant(int32_t rows, int32_t cols, int dir, int precision)
 {
     if (!basic_size_ok(rows, cols)) return DCT2D_ERR_SIZE;
-    if (dir < 0 || dir > 2 || precision < 0 || precision > DCT2D_AUTO) return DCT2D_ERR_ARG;
+    if (dir < 0 || dir > DCT2D_FILTER || precision < 0 || precision > DCT2D_AUTO) return DCT2D_ERR_ARG;
+    if (dir == DCT2D_FILTER && precision != DCT2D_FP32 && precision != DCT2D_AUTO) return DCT2D_ERR_PRECISION;
     // for DCT2D_AUTO the "variant" is the frozen path (a dct2d_precision value)
-    if (precision == DCT2D_AUTO) return resolve_precision(rows, cols, dir, DCT2D_AUTO);
+    if (precision == DCT2D_AUTO) return dir == DCT2D_FILTER ? DCT2D_FP32 : resolve_precision(rows, cols, dir, DCT2D_AUTO);
     return variant_for(rows, cols, dir, precision);
 }
 
 int dct2d_set_variant(int32_t rows, int32_t cols, int dir, int precision, int variant)
 {
     if (!basic_size_ok(rows, cols)) return DCT2D_ERR_SIZE;
-    if (dir < 0 || dir > 2 || precision < 0 || precision > DCT2D_AUTO) return DCT2D_ERR_ARG;
+    if (dir < 0 || dir > DCT2D_FILTER || precision < 0 || precision > DCT2D_AUTO) return DCT2D_ERR_ARG;
+    if (dir == DCT2D_FILTER && precision != DCT2D_FP32) {
+        if (precision != DCT2D_AUTO) return DCT2D_ERR_PRECISION;
+        return variant == DCT2D_FP32 ? DCT2D_OK : DCT2D_ERR_PRECISION; // the filter's only path
+    }
     if (precision == DCT2D_AUTO) {
         // freeze the float32-accurate path used by DCT2D_AUTO
         if (variant != DCT2D_FP32 && variant != DCT2D_SPLIT_BF16X6 && variant != DCT2D_SPLIT_FP16X3)
@@ -245,7 +256,11 @@ int dct2d_set_variant(int32_t rows, int32_t cols, int dir, int precision, int va
 int dct2d_tune(int32_t rows, int32_t cols, int dir, int precision, int64_t batch, void* stream, float* best_ms)
 {
     if (!basic_size_ok(rows, cols)) return DCT2D_ERR_SIZE;
-    if (dir < 0 || dir > 2 || precision < 0 || precision > DCT2D_AUTO || batch <= 0) return DCT2D_ERR_ARG;
+    if (dir < 0 || dir > DCT2D_FILTER || precision < 0 || precision > DCT2D_AUTO || batch <= 0) return DCT2D_ERR_ARG;
+    if (dir == DCT2D_FILTER) {
+        if (precision != DCT2D_FP32 && precision != DCT2D_AUTO) return DCT2D_ERR_PRECISION;
+        precision = DCT2D_FP32; // the filter's only path
+    }
     if (precision == DCT2D_AUTO) {
         // tune every float32-accurate path, then freeze the fastest one for DCT2D_AUTO
         int best_p = -1;
@@ -273,11 +288,13 @@ int dct2d_tune(int32_t rows, int32_t cols, int dir, int precision, int64_t batch
     if (!t) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t n = batch * rows * cols;
-    float *src = nullptr, *dst = nullptr, *ref = nullptr;
-    if (hipMalloc(&src, n * 4) != hipSuccess) return DCT2D_ERR_NOMEM;
+    float *src = nullptr, *dst = nullptr, *ref = nullptr, *lam = nullptr;
+    const int64_t nl = dir == DCT2D_FILTER ? (int64_t)rows * cols : 0; // one shared multiplier array
+    if (hipMalloc(&src, (n + nl) * 4) != hipSuccess) return DCT2D_ERR_NOMEM;
     if (hipMalloc(&dst, n * 4) != hipSuccess) { hipFree(src); return DCT2D_ERR_NOMEM; }
     if (hipMalloc(&ref, n * 4) != hipSuccess) { hipFree(src); hipFree(dst); return DCT2D_ERR_NOMEM; }
-    k_fill<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, n, 0x5eedu);
+    k_fill<<<(unsigned)((n + nl + 255) / 256), 256, 0, s>>>(src, n + nl, 0x5eedu);
+    if (nl) lam = src + n;
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
@@ -286,6 +303,7 @@ int dct2d_tune(int32_t rows, int32_t cols, int dir, int precision, int64_t batch
     float best_t = 0.f;
     for (int v = 0; v < nv && rc == DCT2D_OK; ++v) {
         Job j{dir, src, v == 0 ? ref : dst, batch, rows, cols, rows * (int64_t)cols, rows * (int64_t)cols, s, v};
+        j.lam = lam;
         auto launch = [&]() {
             return precision == DCT2D_FP32 ? launch_fp32(t, j) : launch_mfma(t, j, precision);
         };

@@ -124,7 +124,7 @@ struct Addr {
 // Internal direction of the fused spectral filter (Prop. 1, eq. 4): the round trip
 // with the coefficients multiplied by Addr::lam between the forward and inverse
 // column transforms.  Float32 path only.
-constexpr int DIR_FILTER = 3;
+constexpr int DIR_FILTER = DCT2D_FILTER;
 
 // ---- kernel launchers (each returns a DCT2D_* status) ------------------------------
 struct Job {

@@ -71,3 +71,44 @@ def test_filter_validation_on_host():
     assert lib.dct2d_filter(a, a, 3, 8, 8, 64, 64, ctypes.c_void_p(0x200002), 0, None) == -4  # misaligned
     assert lib.dct2d_filter(a, a, 3, 8, 8, 64, 64, ctypes.c_void_p(0x100100), 0, None) == -1  # overlaps out
     assert lib.dct2d_filter(a, a, -1, 8, 8, 64, 64, ctypes.c_void_p(0x200000), 0, None) == -1  # batch < 0
+
+
+def test_filter_policy_entry_on_host():
+    """The filter's own policy entry (DCT2D_FILTER = 3): float32 only, starts as the round trip's."""
+    lib = dct.load()
+    fp32, bf16x6, auto = 0, 2, 7
+    for n in (8, 64, 128, 256):
+        assert lib.dct2d_variant_count(n, n, 3, fp32) == lib.dct2d_variant_count(n, n, 2, fp32) > 0
+        assert lib.dct2d_variant_count(n, n, 3, bf16x6) == 0
+        assert lib.dct2d_get_variant(n, n, 3, auto) == fp32
+        assert lib.dct2d_get_variant(n, n, 3, fp32) == lib.dct2d_get_variant(n, n, 2, fp32)
+    assert lib.dct2d_get_variant(8, 8, 3, bf16x6) == -5
+    assert lib.dct2d_set_variant(8, 8, 3, bf16x6, 0) == -5
+    assert lib.dct2d_set_variant(8, 8, 3, auto, bf16x6) == -5
+    assert lib.dct2d_set_variant(8, 8, 3, auto, fp32) == 0
+    keep = lib.dct2d_get_variant(8, 8, 3, fp32)
+    assert lib.dct2d_set_variant(8, 8, 3, fp32, 5) == 0
+    assert lib.dct2d_get_variant(8, 8, 3, fp32) == 5
+    assert lib.dct2d_get_variant(8, 8, 2, fp32) != 5 or keep == 5  # the round trip's entry is separate
+    assert lib.dct2d_set_variant(8, 8, 3, fp32, keep) == 0
+    assert lib.dct2d_set_variant(8, 8, 3, fp32, 99) == -1
+    assert lib.dct2d_tune(8, 8, 3, bf16x6, 64, None, None) == -5
+    assert lib.dct2d_variant_count(8, 8, 4, fp32) == 0
+
+
+def test_policy_save_and_load_round_trip(tmp_path):
+    """The autotune cache (policy JSON) holds every direction, the filter's entry included,
+    and loading it back reproduces it (host only)."""
+    pol = dct.policy()
+    assert "64x64/filter/fp32" in pol and pol["64x64/filter/auto"] == dct.FP32
+    path = tmp_path / "pol.json"
+    keep = dct.get_variant(32, 32, "filter", "fp32")
+    try:
+        dct.set_variant(32, 32, "filter", "fp32", (keep + 1) % dct.variant_count(32, 32, "filter", "fp32"))
+        dct.save_policy(str(path))
+        saved = dct.policy()
+        dct.set_variant(32, 32, "filter", "fp32", keep)
+        dct.load_policy(str(path))
+        assert dct.policy() == saved
+    finally:
+        dct.set_variant(32, 32, "filter", "fp32", keep)

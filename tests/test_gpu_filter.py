@@ -95,8 +95,13 @@ def test_unit_multipliers_reproduce_the_round_trip_bitwise(h, w):
     g = np.random.default_rng(h * w)
     x = g.standard_normal((_batch(h, w), h, w)).astype(np.float32)
     t = to_gpu(x)
-    rt = dct.transform(t, None, "roundtrip", "fp32")
-    f = dct.filter(t, to_gpu(np.ones((h, w), np.float32)))
+    keep = dct.get_variant(h, w, "filter", "fp32")
+    dct.set_variant(h, w, "filter", "fp32", dct.get_variant(h, w, "roundtrip", "fp32"))
+    try:
+        rt = dct.transform(t, None, "roundtrip", "fp32")
+        f = dct.filter(t, to_gpu(np.ones((h, w), np.float32)))
+    finally:
+        dct.set_variant(h, w, "filter", "fp32", keep)
     torch.cuda.synchronize()
     assert np.array_equal(rt.cpu().numpy(), f.cpu().numpy())
 
@@ -113,22 +118,41 @@ def test_zero_multipliers_and_zero_blocks(h, w):
 
 
 @pytest.mark.parametrize("h,w", ((8, 8), (32, 32), (64, 64), (128, 128), (256, 256), (8, 64)))
-def test_filter_every_round_trip_variant(h, w):
-    """The filter runs on the round trip's frozen kernel variant; every variant the autotuner
-    may freeze must carry the multiply."""
+def test_filter_every_variant(h, w):
+    """Every kernel variant the autotuner may freeze for the filter carries the multiply."""
     dct = _lib()
     g = np.random.default_rng(h + w)
     x = g.standard_normal((_batch(h, w), h, w)).astype(np.float32)
     lam = g.uniform(-2.0, 2.0, (x.shape[0], h, w)).astype(np.float32)
-    keep = dct.get_variant(h, w, "roundtrip", "fp32")
+    keep = dct.get_variant(h, w, "filter", "fp32")
+    assert dct.variant_count(h, w, "filter", "fp32") == dct.variant_count(h, w, "roundtrip", "fp32")
     try:
-        for v in range(dct.variant_count(h, w, "roundtrip", "fp32")):
-            dct.set_variant(h, w, "roundtrip", "fp32", v)
+        for v in range(dct.variant_count(h, w, "filter", "fp32")):
+            dct.set_variant(h, w, "filter", "fp32", v)
             y, _ = _filter(x, lam)
             e = _score(x, y, lam)
             assert np.isfinite(e).all() and e.max() <= GATE, "%dx%d v%d: %.3e" % (h, w, v, e.max())
     finally:
-        dct.set_variant(h, w, "roundtrip", "fp32", keep)
+        dct.set_variant(h, w, "filter", "fp32", keep)
+
+
+@pytest.mark.parametrize("n", (16, 128))
+def test_filter_tune_freezes_a_variant_that_passes(n):
+    """dct2d_tune on the filter entry measures its variants on scratch data and freezes one;
+    the frozen variant then meets the gate."""
+    dct = _lib()
+    keep = dct.get_variant(n, n, "filter", "fp32")
+    try:
+        ms = dct.tune(n, n, "filter", "fp32", batch=(1 << 22) // (n * n))
+        assert ms > 0
+        assert 0 <= dct.get_variant(n, n, "filter", "fp32") < dct.variant_count(n, n, "filter", "fp32")
+        g = np.random.default_rng(n)
+        x = g.standard_normal((_batch(n, n), n, n)).astype(np.float32)
+        lam = poisson_multipliers(n, n)
+        y, _ = _filter(x, lam)
+        assert _score(x, y, lam).max() <= GATE
+    finally:
+        dct.set_variant(n, n, "filter", "fp32", keep)
 
 
 def test_batch_zero_and_argument_errors():
