@@ -183,3 +183,22 @@ def test_ragged_every_wave_variant(direction):
     finally:
         for n in sizes:
             dct.set_variant(n, n, direction, "fp32", keep[n])
+
+
+@pytest.mark.parametrize("direction", DIRS)
+def test_ragged_non_power_of_two_axes_beyond_384(direction):
+    """Whole images with non-power-of-two axes above 384 (computed exactly from the dense Q_n
+    of eq. 1, no zero-padding; Section 7.1 rejects such axes in the paper's library): 1000,
+    600, 520, 700, 768 and 1020, with even/odd passes where the axis divides by 8 and the
+    plain dense pass otherwise, beside a few hundred blocks."""
+    import torch
+    dct = _lib()
+    images = ((1000, 600), (600, 1000), (520, 700), (768, 768), (8, 1000), (1020, 12))
+    rg = workloads.c4_ragged(blocks=300, images=images, seed=29)
+    plan = dct.RaggedPlan(rg.offsets, rg.rows, rg.cols, direction, "fp32")
+    buf = torch.from_numpy(rg.data).cuda()
+    plan.execute(buf)
+    torch.cuda.synchronize()
+    worst = _check(rg, buf.cpu().numpy(), direction, label="beyond 384")
+    print("ragged beyond-384 %s worst e_rel %.3e" % (direction, worst))
+    plan.close()
