@@ -138,7 +138,8 @@ int dct2d_transform_ex(int dir, const float* in, float* out, int64_t batch, int3
  * Neumann Poisson solve give the least-squares solver step of phase unwrapping.
  * Fused like dct2d_roundtrip: each array is read once and written once, the multiply
  * happens on chip between the forward and inverse transforms, float32 arithmetic on
- * the vector ALU (the DCT2D_FP32 path, with the round trip's frozen kernel variant).
+ * the vector ALU (the DCT2D_FP32 path; its kernel variant is the policy entry of
+ * direction DCT2D_FILTER, which starts as the round trip's and can be tuned).
  *   in, out, batch, rows, cols, in_stride, out_stride: as dct2d_transform_ex (in ==
  *     out allowed; sizes as the basic calls).
  *   lambda: device pointer to the multipliers, row-major with pitch cols, 4-byte
