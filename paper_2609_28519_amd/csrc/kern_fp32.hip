@@ -794,6 +794,9 @@ k_split64(Addr a, int64_t batch, const float2* __restrict__ tw_in)
 //               (right half, x[255-m] = p[m] - q[m])
 //   round trip: in as the forward, rows | per round: forward + inverse column
 //               transforms in registers, then the inverse rows | out as the inverse.
+// In the forward and inverse paths group E reads its round's columns (rows) from the tile
+// during round E but transforms them during round O, beside group O's transforms, instead
+// of leaving group O waiting at the barriers.
 // Every (group, column half) pair runs its own straight-line path; the four paths
 // pass the same sequence of workgroup barriers (forward 12, inverse 14, round trip 18
 // per array).  The array is read whole before its first barrier and written after,
@@ -1015,20 +1018,33 @@ __device__ __forceinline__ void put_row(float* T, int wid, const float (&R)[H])
 }
 
 // Forward transform of tile column cc (256 values down the tile rows): CR 0 -> even
-// coefficients (DCT-II_128 of u), CR 1 -> odd coefficients (DCT-IV_128 of w).
+// coefficients (DCT-II_128 of u), CR 1 -> odd coefficients (DCT-IV_128 of w).  In two
+// parts, so that a group can read its column from the tile before a barrier and transform
+// it after later ones (the transform's input is pinned after the barriers it must follow).
 template <int CR>
-__device__ __forceinline__ void col_fwd(const float* T, int wid, float (&o)[H], twptr tw)
+__device__ __forceinline__ void col_fwd_read(const float* T, int wid, float (&v)[H])
 {
     int cc = lane_t(wid) & 127;
-    float v[H];
 #pragma unroll
     for (int n = 0; n < H; ++n) {
         const float xl = T[n * P + cc], xh = T[(L - 1 - n) * P + cc];
         v[n] = CR == 0 ? xl + xh : xl - xh;
         if (n % 32 == 31) after(cc, v[n]);
     }
+}
+template <int CR>
+__device__ __forceinline__ void col_fwd_tf(float (&v)[H], float (&o)[H], twptr tw)
+{
+    settle(v);
     if constexpr (CR == 0) dct2_rec<L, H>(v, o, tw); else dct4_scaled<L, H>(v, o, tw);
     settle(o);
+}
+template <int CR>
+__device__ __forceinline__ void col_fwd(const float* T, int wid, float (&o)[H], twptr tw)
+{
+    float v[H];
+    col_fwd_read<CR>(T, wid, v);
+    col_fwd_tf<CR>(v, o, tw);
 }
 
 // Inverse of the same column half: CR 0: DCT-III_128 of the even coefficients (a),
@@ -1060,21 +1076,33 @@ __device__ __forceinline__ void put_halves(float* T, int wid, const float (&R)[H
 // Inverse transform of the entries of row i held in the tile as column halves:
 // Z[i][.] = a[r] + b[r] (i < 128, r = i) or a[r] - b[r] (r = 255 - i).  Group 0 has
 // the even entries (DCT-III_128), group 1 the odd entries (DCT-IV_128).
+// (In two parts, like col_fwd.)
 template <int G>
-__device__ __forceinline__ void row_inv(const float* T, int wid, float (&R)[H], twptr tw)
+__device__ __forceinline__ void row_inv_read(const float* T, int wid, float (&o)[H])
 {
     const int i = lane_t(wid) & 255;
     const bool top = i < H;
     int r = top ? i : L - 1 - i;
     const float sg = top ? 1.f : -1.f; // exact: one rounding, as a +- b
-    float o[H];
 #pragma unroll
     for (int c = 0; c < H; ++c) {
         o[c] = __builtin_fmaf(sg, T[(H + r) * P + c], T[r * P + c]);
         if (c % 32 == 31) after(r, o[c]);
     }
+}
+template <int G>
+__device__ __forceinline__ void row_inv_tf(float (&o)[H], float (&R)[H], twptr tw)
+{
+    settle(o);
     if constexpr (G == 0) dct3_rec<L, H>(o, R, tw); else dct4_scaled<L, H>(o, R, tw);
     settle(R);
+}
+template <int G>
+__device__ __forceinline__ void row_inv(const float* T, int wid, float (&R)[H], twptr tw)
+{
+    float o[H];
+    row_inv_read<G>(T, wid, o);
+    row_inv_tf<G>(o, R, tw);
 }
 
 // ---- forward output: coefficient rows 2k + CR (k in half HF of 0..127) of column
@@ -1151,8 +1179,16 @@ __device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, i
             __syncthreads(); // stage reads done
             put_row(T, wid, R);
             __syncthreads();
-            col_fwd<CR>(T, wid, o, tw);
-            syncs(3); // round O
+            {
+                // the columns are read now and transformed beside round O's column
+                // transforms (after its rows are in the tile), where this group would
+                // otherwise wait
+                float v[H];
+                col_fwd_read<CR>(T, wid, v);
+                syncs(2); // round O: its rows into the tile
+                col_fwd_tf<CR>(v, o, tw);
+            }
+            __syncthreads(); // round O
         } else {
             syncs(3); // round E
             put_row(T, wid, R);
@@ -1169,8 +1205,14 @@ __device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, i
                 __syncthreads();
                 put_halves<CR>(T, wid, R);
                 __syncthreads();
-                row_inv<0>(T, wid, R, tw); // p
-                syncs(3);                // round O
+                {
+                    // p: the entries are read now and transformed beside round O's rows
+                    float o[H];
+                    row_inv_read<0>(T, wid, o);
+                    syncs(2); // round O: its halves into the tile
+                    row_inv_tf<0>(o, R, tw);
+                }
+                __syncthreads(); // round O
             } else {
                 syncs(3); // round E
                 put_halves<CR>(T, wid, R);
@@ -1195,6 +1237,8 @@ __device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, i
                 __syncthreads();
                 put_halves<CR>(T, wid, R);
                 __syncthreads();
+                // (deferring this transform into round O, as the forward and inverse paths
+                // do, pushes the round trip past the register file and measured slower)
                 row_inv<0>(T, wid, R, tw); // p
                 syncs(5);                // round O
             } else {
