@@ -1039,12 +1039,20 @@ __device__ __forceinline__ void col_fwd_tf(float (&v)[H], float (&o)[H], twptr t
     if constexpr (CR == 0) dct2_rec<L, H>(v, o, tw); else dct4_scaled<L, H>(v, o, tw);
     settle(o);
 }
+// Both parts in one phase (the transform may start while the last reads are in flight).
 template <int CR>
 __device__ __forceinline__ void col_fwd(const float* T, int wid, float (&o)[H], twptr tw)
 {
+    int cc = lane_t(wid) & 127;
     float v[H];
-    col_fwd_read<CR>(T, wid, v);
-    col_fwd_tf<CR>(v, o, tw);
+#pragma unroll
+    for (int n = 0; n < H; ++n) {
+        const float xl = T[n * P + cc], xh = T[(L - 1 - n) * P + cc];
+        v[n] = CR == 0 ? xl + xh : xl - xh;
+        if (n % 32 == 31) after(cc, v[n]);
+    }
+    if constexpr (CR == 0) dct2_rec<L, H>(v, o, tw); else dct4_scaled<L, H>(v, o, tw);
+    settle(o);
 }
 
 // Inverse of the same column half: CR 0: DCT-III_128 of the even coefficients (a),
@@ -1100,9 +1108,18 @@ __device__ __forceinline__ void row_inv_tf(float (&o)[H], float (&R)[H], twptr t
 template <int G>
 __device__ __forceinline__ void row_inv(const float* T, int wid, float (&R)[H], twptr tw)
 {
+    const int i = lane_t(wid) & 255;
+    const bool top = i < H;
+    int r = top ? i : L - 1 - i;
+    const float sg = top ? 1.f : -1.f; // exact: one rounding, as a +- b
     float o[H];
-    row_inv_read<G>(T, wid, o);
-    row_inv_tf<G>(o, R, tw);
+#pragma unroll
+    for (int c = 0; c < H; ++c) {
+        o[c] = __builtin_fmaf(sg, T[(H + r) * P + c], T[r * P + c]);
+        if (c % 32 == 31) after(r, o[c]);
+    }
+    if constexpr (G == 0) dct3_rec<L, H>(o, R, tw); else dct4_scaled<L, H>(o, R, tw);
+    settle(R);
 }
 
 // ---- forward output: coefficient rows 2k + CR (k in half HF of 0..127) of column
