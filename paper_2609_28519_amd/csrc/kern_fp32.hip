@@ -794,9 +794,9 @@ k_split64(Addr a, int64_t batch, const float2* __restrict__ tw_in)
 //               (right half, x[255-m] = p[m] - q[m])
 //   round trip: in as the forward, rows | per round: forward + inverse column
 //               transforms in registers, then the inverse rows | out as the inverse.
-// In the forward and inverse paths group E reads its round's columns (rows) from the tile
-// during round E but transforms them during round O, beside group O's transforms, instead
-// of leaving group O waiting at the barriers.
+// Group E reads its round's last tile entries (forward: columns; inverse and round trip:
+// rows) during round E but transforms them during round O, beside group O's transforms,
+// instead of leaving group O waiting at the barriers.
 // Every (group, column half) pair runs its own straight-line path; the four paths
 // pass the same sequence of workgroup barriers (forward 12, inverse 14, round trip 18
 // per array).  The array is read whole before its first barrier and written after,
@@ -1254,10 +1254,15 @@ __device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, i
                 __syncthreads();
                 put_halves<CR>(T, wid, R);
                 __syncthreads();
-                // (deferring this transform into round O, as the forward and inverse paths
-                // do, pushes the round trip past the register file and measured slower)
-                row_inv<0>(T, wid, R, tw); // p
-                syncs(5);                // round O
+                {
+                    // p: the entries are read now and transformed beside round O's column
+                    // transforms, where this group would otherwise wait
+                    float o[H];
+                    row_inv_read<0>(T, wid, o);
+                    syncs(2); // round O: its rows into the tile
+                    row_inv_tf<0>(o, R, tw);
+                }
+                syncs(3); // round O
             } else {
                 syncs(5); // round E
                 put_row(T, wid, R);
