@@ -796,7 +796,8 @@ k_split64(Addr a, int64_t batch, const float2* __restrict__ tw_in)
 //               transforms in registers, then the inverse rows | out as the inverse.
 // Group E reads its round's last tile entries (forward: columns; inverse and round trip:
 // rows) during round E but transforms them during round O, beside group O's transforms,
-// instead of leaving group O waiting at the barriers.
+// instead of leaving group O waiting at the barriers; in the round trip, group O's row
+// transform likewise runs during round E's column phase.
 // Every (group, column half) pair runs its own straight-line path; the four paths
 // pass the same sequence of workgroup barriers (forward 12, inverse 14, round trip 18
 // per array).  The array is read whole before its first barrier and written after,
@@ -973,6 +974,29 @@ __device__ __forceinline__ void rows_fwd(const gfloat* src, float* T, int wid, f
     rows_from_stage<G>(T, wid, v, H / 2);
     if constexpr (G == 0) dct2_rec<L, H>(v, R, tw); else dct4_scaled<L, H>(v, R, tw);
     settle(R);
+}
+
+// The staging part of rows_fwd alone (same four barriers): v receives the row entries and
+// the caller transforms them later.
+template <int G>
+__device__ __forceinline__ void rows_fwd_stage(const gfloat* src, float* T, int wid, float (&v)[H])
+{
+    {
+        float qb[64];
+        {
+            float qa[64];
+            load_colhalf<0>(src, wid, qa);
+            __syncthreads(); // earlier readers of the LDS are done
+            put_colhalf(T, wid, qa);
+        }
+        load_colhalf<1>(src, wid, qb);
+        __syncthreads();
+        rows_from_stage<G>(T, wid, v, 0);
+        __syncthreads();
+        put_colhalf(T, wid, qb);
+    }
+    __syncthreads();
+    rows_from_stage<G>(T, wid, v, H / 2);
 }
 
 // ---- inverse columns through the row-half stage: column 2 cc + G; CR 0: even
@@ -1238,9 +1262,9 @@ __device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, i
                 __syncthreads();
             }
         } else {
-            rows_fwd<G>(src, T, wid, R, tw);
-            tw_fence(tw);
             if constexpr (G == 0) {
+                rows_fwd<G>(src, T, wid, R, tw);
+                tw_fence(tw);
                 __syncthreads();
                 put_row(T, wid, R);
                 __syncthreads();
@@ -1264,7 +1288,18 @@ __device__ __forceinline__ void path(const gfloat* src, gfloat* dst, float* T, i
                 }
                 syncs(3); // round O
             } else {
-                syncs(5); // round E
+                {
+                    // the row transform runs during round E's column phase, where this group
+                    // would otherwise wait, instead of beside group E's row transform
+                    float v[H];
+                    rows_fwd_stage<G>(src, T, wid, v);
+                    syncs(2); // round E: stage reads done, its rows into the tile
+                    settle(v);
+                    dct4_scaled<L, H>(v, R, tw);
+                    settle(R);
+                }
+                tw_fence(tw);
+                syncs(3); // round E
                 put_row(T, wid, R);
                 __syncthreads();
                 {
