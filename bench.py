@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--load-policy", default="", help="freeze this saved policy instead of tuning")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch (one graph launch) measurement")
     ap.add_argument("--no-filter", action="store_true", help="skip the spectral-filter measurement")
+    ap.add_argument("--no-rect", action="store_true", help="skip the rectangle-orientation measurement")
     return ap.parse_args()
 
 
@@ -196,6 +197,8 @@ def main():
             del scratch
 
     filt = None if args.no_filter else filter_rates(dct, bufs, host, sizes, stream, per)
+    rect = None if args.no_rect else rect_rates(dct, bufs[sizes[0]], stream,
+                                                tune=not (args.no_tune or args.load_policy))
     ragged = None if args.no_ragged else ragged_c4(dct, stream, args.steps)
     copy_gbs = copy_ceiling(bufs[sizes[0]], stream)
     for n in sizes:
@@ -213,7 +216,7 @@ def main():
            "hbm_frac": round(value / HBM_PEAK_GBS, 4), "copy_ceiling_GBps": round(copy_gbs, 1),
            "wall_s": round(wall, 3),
            "roofline": roofline, "per_size": per, "compare_forward_GBps": compare, "ragged_c4": ragged,
-           "filter": filt}
+           "filter": filt, "rectangles": rect}
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same arrays -----------
     if not args.no_cpu:
@@ -254,6 +257,42 @@ def filter_rates(dct, bufs, host, sizes, stream, per, reps=5):
         res[str(n)] = {"ms": round(ms, 4), "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                        "vs_roundtrip": round(gbs / per[str(n)]["roundtrip"]["GB/s"], 3)}
         del scratch
+    torch.cuda.empty_cache()
+    return res
+
+
+RECT_PAIRS = ((8, 64), (64, 8), (16, 32), (32, 16), (8, 256), (256, 8), (64, 256), (256, 64))
+
+
+def rect_rates(dct, buf, stream, tune=True, reps=5):
+    """Orientation of rectangles (Section 7.1): h x w against w x h on the same 2^27 floats
+    (the batch buffer of the first size, viewed as (2^27 / (h w), h, w)), out of place, float32
+    path, each (shape, direction) autotuned first (untimed) like the square sizes; GB/s of
+    8 h w bytes per array.  Reported beside the step, not part of it."""
+    import torch
+    res = {}
+    scratch = torch.empty_like(buf)
+    for h, w in RECT_PAIRS:
+        batch = buf.numel() // (h * w)
+        x = buf[:batch * h * w].view(batch, h, w)
+        y = scratch[:batch * h * w].view(batch, h, w)
+        res["%dx%d" % (h, w)] = {}
+        for d in DIRS:
+            if tune:
+                dct.tune(h, w, d, "fp32", batch=batch, stream=stream)
+            res["%dx%d" % (h, w)]["variant/" + d] = dct.get_variant(h, w, d, "fp32")
+            dct.transform(x, y, d, "fp32", stream=stream)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                dct.transform(x, y, d, "fp32", stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            res["%dx%d" % (h, w)][d] = round(8 * h * w * batch / (ms * 1e-3) / 1e9, 1)
+    del scratch
     torch.cuda.empty_cache()
     return res
 

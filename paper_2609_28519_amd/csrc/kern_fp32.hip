@@ -1725,8 +1725,8 @@ int fp32_variant_count(int rows, int cols, int)
 // with 512 MiB batches), by the longer axis of arrays up to 64 x 64: 8 staged; 16 staged
 // with at most 16 workgroups per CU; 32 at most 10 per CU, staged for the round trip;
 // 64 x 64 the two-wavefront split kernel, with at most 4 workgroups per CU for forward and
-// inverse (other shapes with a 64 axis: staged, at most 4 per CU, uncapped for the round
-// trip).  The staged split kernel for 128 x 128 with one array per workgroup, the split
+// inverse.  Rectangles with a longer axis of 32: staged, at most 16 per CU; of 64: staged,
+// uncapped (a short axis leaves most lanes of one pass idle, so more resident tiles pay).  The staged split kernel for 128 x 128 with one array per workgroup, the split
 // kernel for 256 x 256 with its two cohorts of CUs staggered by about 6 x 8k cycles.
 int fp32_default_variant(int rows, int cols, int dir)
 {
@@ -1734,6 +1734,7 @@ int fp32_default_variant(int rows, int cols, int dir)
         const int m = rows > cols ? rows : cols;
         const bool rt = dir == DCT2D_ROUNDTRIP;
         if (rows == 64 && cols == 64) return rt ? 13 : 15;
+        if (rows != cols && m >= 32) return m == 32 ? 6 : 4;
         return m <= 8 ? 4 : m <= 16 ? 6 : m <= 32 ? (rt ? 8 : 7) : (rt ? 4 : 12);
     }
     if (rows == 128 && cols == 128) return 4;
