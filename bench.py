@@ -7,10 +7,20 @@ HBM, transformed in place by the forward, inverse and fused round-trip calls of 
 ABI (18 calls).  Algorithmic traffic is one float32 read and one float32 write per
 element per call (8 N^2 bytes per array), so the step moves 18 x 1 GiB.
 
-Reported: whole-step GB/s, per-size/per-direction GB/s and %HBM, the roofline of the
-dominant kernel (HIP-event timing on the stream the kernels run on), a float32 vs
-split-precision matrix-path comparison where it exists, and the FP64 oracle timed on a
-bounded sample of the same arrays on the host cores (the CPU baseline).
+Before any timing, every call is checked on a full-size copy of its batch, on every
+array, against closed forms that need no oracle (the round trip returns its input;
+forward and inverse keep each array's norm and invert each other).
+
+Reported: whole-step GB/s; per size and direction the median over 21 individually
+timed calls with a bootstrap 95 % interval, GB/s, transforms/s and the fractions of
+the 8 TB/s peak and of the library's copy kernel timed in the same run; the
+roofline of the dominant kernel (HIP events on the stream the kernels run on); the
+float32 vs split-precision matrix paths on the C3 arrays (N <= 64) and on the C2
+mixture (65536 16x16 tiles, eight rotating buffer sets) in all three directions; the
+spectral filter, rectangle orientations and the ragged C4 batch.  The CPU-baseline leg
+times the FP64 oracle on a bounded sample of the same arrays on the host cores and
+scores every reported GPU configuration against it (e_rel of Section 6 eq. 5 on
+arrays spread over each batch), plus the boundary diagnostics of Section 6.
 """
 import argparse
 import json
@@ -29,6 +39,9 @@ HBM_PEAK_GBS = 8000.0
 SIZES = (8, 16, 32, 64, 128, 256)
 DIRS = ("forward", "inverse", "roundtrip")
 GATE = {"forward": 2e-6, "inverse": 2e-6, "roundtrip": 4e-6}
+PATHS = ("fp32", "bf16x3", "bf16x6", "fp16x3", "bf16", "fp16", "fp8")
+C2_PATHS = ("fp32", "bf16x3", "bf16x6", "fp16x3")
+SAMPLES = 64  # arrays per configuration scored against the oracle
 
 
 def parse():
@@ -36,12 +49,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--reps", type=int, default=21, help="individually timed calls per case (median, CI)")
     ap.add_argument("--sizes", default=",".join(map(str, SIZES)))
     ap.add_argument("--precision", default="auto", help="path used by the step (auto = library default)")
-    ap.add_argument("--compare", default="fp32,bf16x3,bf16x6,fp16x3,bf16,fp16,fp8",
-                    help="paths timed per size for the float32 vs split comparison (N<=32 for splits)")
-    ap.add_argument("--cpu-frac", type=float, default=0.75, help="fraction of each batch the oracle runs on")
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--compare", default=",".join(PATHS),
+                    help="paths timed per size (N<=64) for the float32 vs split comparison")
+    ap.add_argument("--cpu-frac", type=float, default=0.75, help="fraction of each batch the oracle is timed on")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (timing and every e_rel)")
     ap.add_argument("--log2-floats", type=int, default=27, help="floats per size (default 2^27 = 512 MiB)")
     ap.add_argument("--no-tune", action="store_true", help="skip the (untimed) autotuning pass")
     ap.add_argument("--save-policy", default="", help="write the tuned policy (autotune cache, JSON) here")
@@ -49,8 +63,99 @@ def parse():
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch (one graph launch) measurement")
     ap.add_argument("--no-filter", action="store_true", help="skip the spectral-filter measurement")
     ap.add_argument("--no-rect", action="store_true", help="skip the rectangle-orientation measurement")
+    ap.add_argument("--no-c2", action="store_true", help="skip the C2 mixture timing")
     return ap.parse_args()
 
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+# ---- timing statistics ----------------------------------------------------------------------
+
+def median_ci(ms, boot=2000, seed=0):
+    """Median of the timings and a bootstrap 95 % interval of the median."""
+    a = np.asarray(ms, np.float64)
+    g = np.random.default_rng(seed)
+    meds = np.median(a[g.integers(0, a.size, (boot, a.size))], axis=1)
+    return float(np.median(a)), float(np.percentile(meds, 2.5)), float(np.percentile(meds, 97.5))
+
+
+def time_calls(fn, reps, stream):
+    """Times `reps` calls of fn(i) one by one with HIP events on `stream`; list of ms."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for i, (a, b) in enumerate(ev):
+        a.record(stream)
+        fn(i)
+        b.record(stream)
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in ev]
+
+
+def rate(nbytes, ms, transforms=None, copy_gbs=None):
+    """GB/s row of one case from its timings (median over reps, 95 % bootstrap interval)."""
+    med, lo, hi = median_ci(ms)
+    gbs = nbytes / (med * 1e-3) / 1e9
+    row = {"ms": round(med, 5), "ms_ci95": [round(lo, 5), round(hi, 5)], "reps": len(ms),
+           "GB/s": round(gbs, 1), "GB/s_ci95": [round(nbytes / (hi * 1e-3) / 1e9, 1),
+                                               round(nbytes / (lo * 1e-3) / 1e9, 1)],
+           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    if transforms is not None:
+        row["transforms_per_s"] = round(transforms / (med * 1e-3), 1)
+    if copy_gbs:
+        row["copy_frac"] = round(gbs / copy_gbs, 4)
+    return row
+
+
+# ---- pre-timing self-check (closed forms, no oracle) ------------------------------------------
+
+def per_array(t, ref):
+    """||t_i - ref_i|| / ||ref_i|| over every array (float64 on the GPU)."""
+    import torch
+    d = (t.double() - ref.double()).reshape(t.shape[0], -1)
+    n = ref.double().reshape(ref.shape[0], -1)
+    return torch.linalg.vector_norm(d, dim=1) / torch.linalg.vector_norm(n, dim=1)
+
+
+def norm_change(t, ref):
+    import torch
+    a = torch.linalg.vector_norm(t.double().reshape(t.shape[0], -1), dim=1)
+    b = torch.linalg.vector_norm(ref.double().reshape(ref.shape[0], -1), dim=1)
+    return (a - b).abs() / b
+
+
+def self_check(dct, bufs, sizes, precision, stream):
+    """Every call the step times, on a full-size copy, in its timed launch configuration; every
+    array checked.  Round trip: returns its input within 4e-6.  Forward (inverse): keeps each
+    array's norm within 2e-6, and the opposite call returns the input within 4e-6."""
+    report = {}
+    for n in sizes:
+        x = bufs[n]
+        worst = {}
+        t = x.clone()
+        dct.transform(t, t, "roundtrip", precision, stream=stream)
+        worst["roundtrip"] = float(per_array(t, x).max())
+        for d, back in (("forward", "inverse"), ("inverse", "forward")):
+            t.copy_(x)
+            dct.transform(t, t, d, precision, stream=stream)
+            worst[d + "_norm"] = float(norm_change(t, x).max())
+            dct.transform(t, t, back, precision, stream=stream)
+            worst[d + "_then_" + back] = float(per_array(t, x).max())
+        del t
+        ok = (worst["roundtrip"] <= GATE["roundtrip"] and worst["forward_norm"] <= GATE["forward"]
+              and worst["inverse_norm"] <= GATE["inverse"] and worst["forward_then_inverse"] <= GATE["roundtrip"]
+              and worst["inverse_then_forward"] <= GATE["roundtrip"])
+        if not ok:
+            log("self-check failed N=%d: %s" % (n, worst))
+            sys.exit(1)
+        report[str(n)] = {k: float("%.3e" % v) for k, v in worst.items()}
+    import torch
+    torch.cuda.empty_cache()
+    return report
+
+
+# ---- main -----------------------------------------------------------------------------------
 
 def main():
     args = parse()
@@ -69,7 +174,7 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
 
-    # ---- inputs resident in HBM ------------------------------------------------------
+    # ---- inputs resident in HBM ----------------------------------------------------------
     host = {}
     bufs = {}
     for n in sizes:
@@ -77,10 +182,10 @@ def main():
         x = workloads.c3_normal(n, batch=batch).x
         host[n] = x
         bufs[n] = torch.from_numpy(x).to(dev)
-        print("input N=%d batch=%d (%.0f MiB)" % (n, batch, x.nbytes / 2 ** 20), file=sys.stderr, flush=True)
+        log("input N=%d batch=%d (%.0f MiB)" % (n, batch, x.nbytes / 2 ** 20))
     torch.cuda.synchronize()
 
-    # ---- autotune (untimed, on the library's own scratch data, before any measurement) --
+    # ---- autotune (untimed, on the library's own scratch data, before any measurement) ----
     tuned = {}
     if args.load_policy:
         dct.load_policy(args.load_policy)
@@ -92,6 +197,7 @@ def main():
             if not args.no_filter:
                 dct.tune(n, n, "filter", "fp32", batch=(1 << args.log2_floats) // (n * n), stream=stream)
         torch.cuda.synchronize()
+        log("tuned")
     if args.save_policy:
         dct.save_policy(args.save_policy)
     for n in sizes:
@@ -104,21 +210,10 @@ def main():
     def call(n, d, prec, t):
         return dct.transform(t, t, d, prec, stream=stream)
 
-    # ---- self-check before timing (the round trip must return the input) -------------
-    # Runs on a full-size copy so every launch of a kernel in this process has the same size.
-    for n in sizes:
-        t = bufs[n].clone()
-        call(n, "roundtrip", args.precision, t)
-        torch.cuda.synchronize()
-        num = torch.linalg.vector_norm((t[:256] - bufs[n][:256]).double().reshape(256, -1), dim=1)
-        den = torch.linalg.vector_norm(bufs[n][:256].double().reshape(256, -1), dim=1)
-        worst = float((num / den).max())
-        del t
-        if worst > GATE["roundtrip"]:
-            print("self-check failed N=%d e_rel %.3e" % (n, worst), file=sys.stderr)
-            sys.exit(1)
+    checked = self_check(dct, bufs, sizes, args.precision, stream)
+    log("self-check passed")
 
-    # ---- warmup + timed steps ----------------------------------------------------------
+    # ---- warmup + timed steps --------------------------------------------------------------
     for _ in range(args.warmup):
         for n in sizes:
             for d in DIRS:
@@ -146,64 +241,50 @@ def main():
     ms_per_step = total_ms / args.steps
     bytes_per_step = sum(8 * n * n * host[n].shape[0] for n in sizes) * len(DIRS)
     value = bytes_per_step / (ms_per_step * 1e-3) / 1e9
+    step_call_ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
+    log("timed %d steps: %.3f ms/step" % (args.steps, ms_per_step))
 
+    # ---- the copy ceiling (library kernel, same run) ---------------------------------------
+    copy_rows = copy_ceiling(dct, bufs[sizes[0]], stream, args.reps)
+    copy_gbs = copy_rows["out_of_place"]["GB/s"]
+
+    # ---- per-case statistics: 21 individually timed calls each -------------------------------
     per = {}
-    call_ms = {}
     for n in sizes:
         per[str(n)] = {}
+        nb = 8 * n * n * host[n].shape[0]
         for d in DIRS:
-            ms = float(np.mean([a.elapsed_time(b) for a, b in ev[(n, d)]]))
-            call_ms[(n, d)] = ms
-            gbs = 8 * n * n * host[n].shape[0] / (ms * 1e-3) / 1e9
-            per[str(n)][d] = {"ms": round(ms, 4), "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                              "transforms_per_s": round(host[n].shape[0] / (ms * 1e-3), 1)}
+            ms = time_calls(lambda i: call(n, d, args.precision, bufs[n]), args.reps, stream)
+            per[str(n)][d] = rate(nb, ms, host[n].shape[0], copy_gbs)
+            per[str(n)][d]["step_mean_ms"] = round(step_call_ms[(n, d)], 5)
+            per[str(n)][d]["variant"] = tuned["%d/%s" % (n, d)]
 
     # dominant kernel: the call with the largest share of the step among calls that are one
-    # kernel launch (the event pair then brackets exactly that kernel)
+    # kernel launch (the event pair then brackets exactly that kernel); its average over the
+    # timed steps
     names = {(n, d): kernel_name(n, d, tuned["%d/%s" % (n, d)]) for n in sizes for d in DIRS}
     single = [k for k in names if names[k]]
-    dom = max(single, key=lambda k: call_ms[k]) if single else max(call_ms, key=call_ms.get)
+    dom = max(single, key=lambda k: step_call_ms[k]) if single else max(step_call_ms, key=step_call_ms.get)
     n_dom, d_dom = dom
     alg_bytes = 8 * n_dom * n_dom * host[n_dom].shape[0]
-    achieved = alg_bytes / (call_ms[dom] * 1e-3) / 1e9
+    achieved = alg_bytes / (step_call_ms[dom] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": counted_traffic(names[dom]) if names.get(dom) else None,
                 "kernel": names.get(dom) or "%s N=%d" % (d_dom, n_dom), "call": "%s N=%d" % (d_dom, n_dom),
-                "avg_ms": round(call_ms[dom], 4), "algorithmic_bytes_per_launch": alg_bytes}
+                "avg_ms": round(step_call_ms[dom], 5), "algorithmic_bytes_per_launch": alg_bytes,
+                "copy_frac": round(achieved / copy_gbs, 4)}
 
-    # ---- float32 vs split-precision matrix paths (same GPU, same inputs) --------------
-    compare = {}
-    for p in [c for c in args.compare.split(",") if c]:
-        for n in sizes:
-            if p != "fp32" and n > 64:
-                continue
-            scratch = torch.empty_like(bufs[n])
-            try:
-                dct.transform(bufs[n], scratch, "forward", p, stream=stream)
-            except dct.DCT2DError:
-                continue
-            torch.cuda.synchronize()
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            reps = 5
-            a.record(stream)
-            for _ in range(reps):
-                dct.transform(bufs[n], scratch, "forward", p, stream=stream)
-            b.record(stream)
-            torch.cuda.synchronize()
-            ms = a.elapsed_time(b) / reps
-            compare.setdefault(p, {})[str(n)] = round(8 * n * n * host[n].shape[0] / (ms * 1e-3) / 1e9, 1)
-            del scratch
-
-    filt = None if args.no_filter else filter_rates(dct, bufs, host, sizes, stream, per)
+    # ---- float32 vs split-precision matrix paths on the C3 arrays (N <= 64) -------------------
+    compare = compare_paths(dct, bufs, host, sizes, [p for p in args.compare.split(",") if p], stream, args.reps,
+                            copy_gbs)
+    c2 = None if args.no_c2 else c2_rates(dct, stream, args.reps, copy_gbs)
+    filt = None if args.no_filter else filter_rates(dct, bufs, host, sizes, stream, per, args.reps)
     rect = None if args.no_rect else rect_rates(dct, bufs[sizes[0]], stream,
                                                 tune=not (args.no_tune or args.load_policy))
-    ragged = None if args.no_ragged else ragged_c4(dct, stream, args.steps)
-    copy_gbs = copy_ceiling(bufs[sizes[0]], stream)
-    for n in sizes:
-        for d in DIRS:
-            per[str(n)][d]["copy_frac"] = round(per[str(n)][d]["GB/s"] / copy_gbs, 4)
+    ragged = None if args.no_ragged else ragged_c4(dct, stream, args.reps)
+    del bufs
+    torch.cuda.empty_cache()
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
@@ -214,14 +295,82 @@ def main():
                       "sizes": sizes, "batch": {str(n): int(host[n].shape[0]) for n in sizes},
                       "precision": args.precision, "variants": tuned},
            "hbm_frac": round(value / HBM_PEAK_GBS, 4), "copy_ceiling_GBps": round(copy_gbs, 1),
-           "wall_s": round(wall, 3),
-           "roofline": roofline, "per_size": per, "compare_forward_GBps": compare, "ragged_c4": ragged,
+           "copy": copy_rows, "wall_s": round(wall, 3), "self_check": checked,
+           "roofline": roofline, "per_size": per, "compare": compare, "c2_mixture": c2, "ragged_c4": ragged,
            "filter": filt, "rectangles": rect}
 
-    # ---- CPU baseline: the FP64 oracle on a bounded sample of the same arrays -----------
+    # ---- CPU baseline: the FP64 oracle timed on the host, and every row scored against it ------
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(host, sizes, args.cpu_frac, bufs, stream)
+        out["cpu_baseline"] = cpu_baseline(dct, host, sizes, args, out, stream)
     print(json.dumps(out), flush=True)
+
+
+# ---- reported beside the step -------------------------------------------------------------------
+
+def copy_ceiling(dct, buf, stream, reps):
+    """The library's reference copy kernel (dct2d_copy) over one 512 MiB buffer, out of place and in
+    place: one read and one write per element, the practical ceiling of a transform."""
+    import torch
+    out = torch.empty_like(buf)
+    dct.copy(buf, out, stream=stream)
+    nb = 2 * buf.numel() * 4
+    rows = {"out_of_place": rate(nb, time_calls(lambda i: dct.copy(buf, out, stream=stream), reps, stream))}
+    rows["in_place"] = rate(nb, time_calls(lambda i: dct.copy(out, out, stream=stream), reps, stream))
+    del out
+    torch.cuda.empty_cache()
+    return rows
+
+
+def compare_paths(dct, bufs, host, sizes, paths, stream, reps, copy_gbs):
+    """Every arithmetic path on the same C3 arrays (N <= 64), out of place, all three directions."""
+    import torch
+    res = {}
+    for n in sizes:
+        if n > 64:
+            continue
+        scratch = torch.empty_like(bufs[n])
+        for p in paths:
+            for d in DIRS:
+                try:
+                    dct.transform(bufs[n], scratch, d, p, stream=stream)
+                except dct.DCT2DError:
+                    continue
+                ms = time_calls(lambda i: dct.transform(bufs[n], scratch, d, p, stream=stream), reps, stream)
+                res.setdefault(p, {}).setdefault(str(n), {})[d] = rate(8 * n * n * host[n].shape[0], ms,
+                                                                      host[n].shape[0], copy_gbs)
+        del scratch
+    torch.cuda.empty_cache()
+    return res
+
+
+C2_SETS = 8
+
+
+def c2_rates(dct, stream, reps, copy_gbs):
+    """The C2 mixture (65536 16x16 tiles: uniform, normal, ramps with a 1e-6 component, 2^+-100
+    amplitudes) through the float32 and split-precision paths in all three directions, out of place,
+    rotating over 8 buffer sets (512 MiB of inputs) so the 256 MB memory-side cache cannot serve
+    them."""
+    import torch
+
+    import workloads
+    sets = [torch.from_numpy(workloads.c2_mixture16(seed=workloads.SEEDS["c2"] + s).x).cuda()
+            for s in range(C2_SETS)]
+    outs = [torch.empty_like(sets[0]) for _ in range(C2_SETS)]
+    nb = 8 * sets[0].numel()
+    res = {}
+    for p in C2_PATHS:
+        for d in DIRS:
+            try:
+                dct.transform(sets[0], outs[0], d, p, stream=stream)
+            except dct.DCT2DError:
+                continue
+            ms = time_calls(lambda i: dct.transform(sets[i % C2_SETS], outs[i % C2_SETS], d, p, stream=stream),
+                            reps, stream)
+            res.setdefault(p, {})[d] = rate(nb, ms, sets[0].shape[0], copy_gbs)
+    del sets, outs
+    torch.cuda.empty_cache()
+    return res
 
 
 def poisson_multipliers(n):
@@ -234,7 +383,7 @@ def poisson_multipliers(n):
     return lam.astype(np.float32)
 
 
-def filter_rates(dct, bufs, host, sizes, stream, per, reps=5):
+def filter_rates(dct, bufs, host, sizes, stream, per, reps):
     """The fused spectral filter (Prop. 1, eq. 4) on the same batches, one shared Poisson
     operator, out of place: one read and one write per array like the round trip, so its
     GB/s uses the same 8 N^2 bytes per array.  Reported beside the step, not part of it."""
@@ -244,18 +393,9 @@ def filter_rates(dct, bufs, host, sizes, stream, per, reps=5):
         lam = torch.from_numpy(poisson_multipliers(n)).to(bufs[n].device)
         scratch = torch.empty_like(bufs[n])
         dct.filter(bufs[n], lam, out=scratch, stream=stream)
-        torch.cuda.synchronize()
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(reps):
-            dct.filter(bufs[n], lam, out=scratch, stream=stream)
-        b.record(stream)
-        torch.cuda.synchronize()
-        ms = a.elapsed_time(b) / reps
-        gbs = 8 * n * n * host[n].shape[0] / (ms * 1e-3) / 1e9
-        res[str(n)] = {"ms": round(ms, 4), "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                       "vs_roundtrip": round(gbs / per[str(n)]["roundtrip"]["GB/s"], 3)}
+        ms = time_calls(lambda i: dct.filter(bufs[n], lam, out=scratch, stream=stream), reps, stream)
+        res[str(n)] = rate(8 * n * n * host[n].shape[0], ms, host[n].shape[0])
+        res[str(n)]["vs_roundtrip"] = round(res[str(n)]["GB/s"] / per[str(n)]["roundtrip"]["GB/s"], 3)
         del scratch
     torch.cuda.empty_cache()
     return res
@@ -264,7 +404,7 @@ def filter_rates(dct, bufs, host, sizes, stream, per, reps=5):
 RECT_PAIRS = ((8, 64), (64, 8), (16, 32), (32, 16), (8, 256), (256, 8), (64, 256), (256, 64))
 
 
-def rect_rates(dct, buf, stream, tune=True, reps=5):
+def rect_rates(dct, buf, stream, tune=True, reps=9):
     """Orientation of rectangles (Section 7.1): h x w against w x h on the same 2^27 floats
     (the batch buffer of the first size, viewed as (2^27 / (h w), h, w)), out of place, float32
     path, each (shape, direction) autotuned first (untimed) like the square sizes; GB/s of
@@ -276,45 +416,40 @@ def rect_rates(dct, buf, stream, tune=True, reps=5):
         batch = buf.numel() // (h * w)
         x = buf[:batch * h * w].view(batch, h, w)
         y = scratch[:batch * h * w].view(batch, h, w)
-        res["%dx%d" % (h, w)] = {}
+        key = "%dx%d" % (h, w)
+        res[key] = {}
         for d in DIRS:
             if tune:
                 dct.tune(h, w, d, "fp32", batch=batch, stream=stream)
-            res["%dx%d" % (h, w)]["variant/" + d] = dct.get_variant(h, w, d, "fp32")
+            res[key]["variant/" + d] = dct.get_variant(h, w, d, "fp32")
             dct.transform(x, y, d, "fp32", stream=stream)
-            torch.cuda.synchronize()
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            for _ in range(reps):
-                dct.transform(x, y, d, "fp32", stream=stream)
-            b.record(stream)
-            torch.cuda.synchronize()
-            ms = a.elapsed_time(b) / reps
-            res["%dx%d" % (h, w)][d] = round(8 * h * w * batch / (ms * 1e-3) / 1e9, 1)
+            ms = time_calls(lambda i: dct.transform(x, y, d, "fp32", stream=stream), reps, stream)
+            res[key][d] = rate(8 * h * w * batch, ms, batch)
     del scratch
     torch.cuda.empty_cache()
     return res
 
 
-def copy_ceiling(buf, stream, reps=10):
-    """GB/s of a plain device-to-device copy of one 512 MiB buffer (read + write bytes), the practical
-    ceiling a one-read-one-write kernel is compared against."""
+def ragged_c4(dct, stream, reps):
+    """The ragged configuration: 200k blocks (8..256) + 4 x 1024^2 + 4 x 512x384 images, U[-1,1] with 5%
+    of items x 1e30, forward in place, one hipGraphLaunch per execution (plan recorded before timing)."""
     import torch
-    out = torch.empty_like(buf)
-    out.copy_(buf)
-    torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    for _ in range(reps):
-        out.copy_(buf)
-    b.record(stream)
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / reps
-    del out
+
+    import workloads
+    rg = workloads.c4_ragged()
+    buf = torch.from_numpy(rg.data).cuda()
+    plan = dct.RaggedPlan(rg.offsets, rg.rows, rg.cols, "forward", "auto")
+    info = plan.info()
+    plan.execute(buf, stream)
+    ms = time_calls(lambda i: plan.execute(buf, stream), reps, stream)
+    alg = int(8 * (rg.rows.astype(np.int64) * rg.cols).sum())
+    plan.close()
+    del buf
     torch.cuda.empty_cache()
-    return 2 * buf.numel() * 4 / (ms * 1e-3) / 1e9
+    row = rate(alg, ms, rg.count)
+    row.update({"items": info["items"], "classes": info["classes"], "graph_nodes": info["graph_nodes"],
+                "launches_per_execution": 1, "algorithmic_bytes": alg})
+    return row
 
 
 def kernel_name(n, d, tuned):
@@ -341,15 +476,18 @@ def kernel_name(n, d, tuned):
     return None
 
 
+KERNEL_SOURCES = ("kern_fp32.hip", "dct1d.hpp", "internal.hpp")
+
+
 def source_digest():
-    """SHA-256 over the kernel sources; ties counter-derived traffic figures to the code they measured."""
+    """SHA-256 over the sources of the float32 transform kernels; ties counter-derived traffic figures
+    to the kernel code they measured."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2609_28519_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
@@ -369,73 +507,177 @@ def counted_traffic(kernel):
     return int(k["read_bytes"] + k["write_bytes"])
 
 
-def ragged_c4(dct, stream, steps):
-    """The ragged configuration: 200k blocks (8..256) + 4 x 1024^2 + 4 x 512x384 images, U[-1,1] with 5%
-    of items x 1e30, forward in place, one hipGraphLaunch per step (plan recorded before timing)."""
-    import torch
+# ---- the oracle leg ------------------------------------------------------------------------------
 
-    import workloads
-    rg = workloads.c4_ragged()
-    buf = torch.from_numpy(rg.data).cuda()
-    plan = dct.RaggedPlan(rg.offsets, rg.rows, rg.cols, "forward", "auto")
-    info = plan.info()
-    plan.execute(buf, stream)
-    torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    for _ in range(steps):
-        plan.execute(buf, stream)
-    b.record(stream)
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / steps
-    alg = int(8 * (rg.rows.astype(np.int64) * rg.cols).sum())
-    plan.close()
-    del buf
-    torch.cuda.empty_cache()
-    return {"ms": round(ms, 4), "GB/s": round(alg / (ms * 1e-3) / 1e9, 1),
-            "hbm_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "items": info["items"],
-            "classes": info["classes"], "graph_nodes": info["graph_nodes"], "launches_per_step": 1,
-            "algorithmic_bytes": alg}
+def spread(batch, k, seed):
+    """About k array indices spread over the whole batch (one per equal segment, first and last)."""
+    g = np.random.default_rng(seed)
+    k = max(1, min(k, batch))
+    edges = np.linspace(0, batch, k + 1).astype(np.int64)
+    idx = [int(g.integers(lo, hi)) for lo, hi in zip(edges[:-1], edges[1:]) if hi > lo]
+    return np.unique(np.array(idx + [0, batch - 1], dtype=np.int64))
 
 
-def cpu_baseline(host, sizes, frac, bufs, stream):
-    """Times the FP64 oracle (as it stands) on the first `frac` of every size's arrays, on the host's
-    cores, for forward, inverse and round trip; also scores the GPU forward of that sample."""
-    import torch
-
+def cpu_baseline(dct, host, sizes, args, out, stream):
+    """Times the FP64 oracle (as it stands) on the first `cpu_frac` of every size's arrays, on the host's
+    cores, for forward, inverse and round trip; then scores the GPU result of every reported
+    configuration against the oracle: the calls are repeated once on fresh copies of their inputs in
+    the launch configuration that was timed, and arrays spread over each batch are compared (e_rel of
+    Section 6 eq. 5; the round trip against its input).  The errors are written into the rows above."""
     import oracle
-    import paper_2609_28519_amd as dct
-
     threads = oracle.default_threads()
     total_bytes = 0
     total_s = 0.0
-    worst = {}
     for n in sizes:
-        m = max(1, int(host[n].shape[0] * frac))
+        m = max(1, int(host[n].shape[0] * args.cpu_frac))
         xs = host[n][:m]
         t0 = time.perf_counter()
-        y = oracle.forward(xs, threads=threads)
+        oracle.forward(xs, threads=threads)
         oracle.inverse(xs, threads=threads)
         oracle.roundtrip(xs, threads=threads)
         total_s += time.perf_counter() - t0
         total_bytes += 8 * n * n * m * 3
-        # error of the GPU calls on part of the sample, vs the oracle (stated for every result): the
-        # forward against the oracle's forward, the inverse of the same arrays read as spectra against
-        # the oracle's inverse, the fused round trip against the input itself
-        k = min(m, 256)
-        ref = {"forward": y[:k], "inverse": oracle.inverse(xs[:k], threads=threads),
-               "roundtrip": xs[:k].astype(np.float64)}
-        worst[str(n)] = {}
+    log("oracle timed: %.1f s" % total_s)
+    res = {"value": round(total_bytes / total_s / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+           "sample": "first %.0f%% of each size's C3 batch (forward + inverse + round trip, FP64 direct "
+                     "definition, %d threads)" % (100 * args.cpu_frac, threads),
+           "seconds": round(total_s, 2)}
+    res["e_rel_max"] = score_all(dct, oracle, host, sizes, args, out, stream)
+    return res
+
+
+def _refs(oracle, xs):
+    return {"forward": oracle.forward(xs), "inverse": oracle.inverse(xs), "roundtrip": xs.astype(np.float64)}
+
+
+def _sampled_output(dct, x_host, idx, d, prec, stream, inplace=True):
+    import torch
+    t = torch.from_numpy(x_host).cuda()
+    o = t if inplace else torch.empty_like(t)
+    dct.transform(t, o, d, prec, stream=stream)
+    torch.cuda.synchronize()
+    y = o[torch.from_numpy(idx).cuda()].cpu().numpy()
+    del t, o
+    return y
+
+
+def score_all(dct, oracle, host, sizes, args, out, stream):
+    """e_rel (max over sampled arrays) of every row; also written into each row as "e_rel"."""
+    import torch
+
+    import workloads
+    summary = {}
+    # the step's calls, in place, full size
+    for n in sizes:
+        idx = spread(host[n].shape[0], SAMPLES, n)
+        xs = host[n][idx]
+        refs = _refs(oracle, xs)
         for d in DIRS:
-            g = torch.from_numpy(xs[:k]).cuda()
-            dct.transform(g, g, d, "auto", stream=stream)
+            e = float(oracle.e_rel(_sampled_output(dct, host[n], idx, d, args.precision, stream), refs[d], xs).max())
+            out["per_size"][str(n)][d]["e_rel"] = float("%.3e" % e)
+            out["per_size"][str(n)][d]["gate"] = GATE[d]
+            summary["%d/%s" % (n, d)] = float("%.3e" % e)
+        # every compared path (out of place, as timed)
+        for p, rows in out["compare"].items():
+            if str(n) in rows:
+                for d in rows[str(n)]:
+                    e = float(oracle.e_rel(_sampled_output(dct, host[n], idx, d, p, stream, False), refs[d],
+                                           xs).max())
+                    rows[str(n)][d]["e_rel"] = float("%.3e" % e)
+        torch.cuda.empty_cache()
+    log("scored the step and the paths")
+    # C2 mixture: the first buffer set, every tile, per category, plus the weak-component error
+    if out.get("c2_mixture"):
+        bt = workloads.c2_mixture16()
+        refs = _refs(oracle, bt.x)
+        ramp = np.flatnonzero(bt.category == workloads.CAT_RAMP_WEAK)
+        for p, rows in out["c2_mixture"].items():
+            for d in rows:
+                y = _sampled_output(dct, bt.x, np.arange(bt.x.shape[0]), d, p, stream, False)
+                e = oracle.e_rel(y, refs[d], bt.x)
+                rows[d]["e_rel"] = float("%.3e" % e.max())
+                rows[d]["e_rel_by_category"] = {int(c): float("%.3e" % e[bt.category == c].max())
+                                                for c in np.unique(bt.category)}
+                if d == "forward":
+                    w = [oracle.weak_component_error(y[i], refs[d][i], *bt.weak_kl[i]) for i in ramp]
+                    rows[d]["weak_component_rel_error"] = {"median": float("%.3e" % np.median(w)),
+                                                           "max": float("%.3e" % np.max(w))}
+        log("scored C2")
+    # filter (Poisson operator), out of place: ||X'_gpu - X'_oracle|| / (max|L| ||X||)
+    if out.get("filter"):
+        for n in sizes:
+            idx = spread(host[n].shape[0], SAMPLES, 3 * n)
+            xs = host[n][idx]
+            lam = poisson_multipliers(n)
+            t = torch.from_numpy(host[n]).cuda()
+            o = dct.filter(t, torch.from_numpy(lam).cuda(), stream=stream)
             torch.cuda.synchronize()
-            worst[str(n)][d] = float(oracle.e_rel(g.cpu().numpy(), ref[d], xs[:k]).max())
-    return {"value": round(total_bytes / total_s / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": "first %.0f%% of each size's batch (forward + inverse + round trip, FP64 direct definition)"
-                      % (100 * frac),
-            "seconds": round(total_s, 2), "gpu_max_e_rel_vs_oracle": worst}
+            y = o[torch.from_numpy(idx).cuda()].cpu().numpy()
+            del t, o
+            ref = oracle.filter(xs, lam.astype(np.float64))
+            num = np.sqrt(((y - ref) ** 2).sum(axis=(1, 2)))
+            den = np.abs(lam).max() * np.sqrt((xs.astype(np.float64) ** 2).sum(axis=(1, 2)))
+            out["filter"][str(n)]["e_rel"] = float("%.3e" % (num / den).max())
+        torch.cuda.empty_cache()
+    # rectangles, out of place, in the tuned variants
+    if out.get("rectangles"):
+        base = host[sizes[0]].reshape(-1)
+        for key, row in out["rectangles"].items():
+            h, w = (int(v) for v in key.split("x"))
+            batch = base.size // (h * w)
+            x = base[:batch * h * w].reshape(batch, h, w)
+            idx = spread(batch, 32, h * 7 + w)
+            xs = x[idx]
+            refs = _refs(oracle, xs)
+            for d in DIRS:
+                y = _sampled_output(dct, x, idx, d, "fp32", stream, False)
+                row[d]["e_rel"] = float("%.3e" % oracle.e_rel(y, refs[d], xs).max())
+        torch.cuda.empty_cache()
+    # ragged C4: per shape class, up to 24 items (2 per image class)
+    if out.get("ragged_c4"):
+        rg = workloads.c4_ragged()
+        buf = torch.from_numpy(rg.data).cuda()
+        plan = dct.RaggedPlan(rg.offsets, rg.rows, rg.cols, "forward", "auto")
+        plan.execute(buf, stream)
+        torch.cuda.synchronize()
+        got = buf.cpu().numpy()
+        plan.close()
+        del buf
+        by_class = {}
+        g = np.random.default_rng(4)
+        shapes = sorted(set(zip(rg.rows.tolist(), rg.cols.tolist())))
+        for h, w in shapes:
+            members = np.flatnonzero((rg.rows == h) & (rg.cols == w))
+            pick = members if members.size <= 2 else g.choice(members, 2 if max(h, w) > 256 else 24, replace=False)
+            worst = 0.0
+            for i in pick:
+                xi = rg.item(int(i))
+                yi = rg.item(int(i), got)
+                worst = max(worst, float(oracle.e_rel(yi, oracle.forward(xi), xi)[0]))
+            by_class["%dx%d" % (h, w)] = float("%.3e" % worst)
+        out["ragged_c4"]["e_rel_by_class"] = by_class
+        out["ragged_c4"]["e_rel"] = max(by_class.values())
+        torch.cuda.empty_cache()
+    # boundary diagnostics (Section 6), reported, not gated
+    diag = {}
+    for n in sizes:
+        bs = workloads.boundary_set(n)
+        finite = [i for i in range(bs.x.shape[0]) if np.isfinite(bs.x[i]).all()]
+        refs = _refs(oracle, bs.x[finite])
+        cell = {}
+        for d in DIRS:
+            y = _sampled_output(dct, bs.x, np.arange(bs.x.shape[0]), d, args.precision, stream, False)
+            for i, name in enumerate(workloads.BOUNDARY_CASES):
+                fin = float(np.isfinite(y[i]).mean())
+                entry = {"finite_frac": round(fin, 4)}
+                if i in finite and fin == 1.0:
+                    with np.errstate(all="ignore"):
+                        entry["e_rel"] = float("%.3e" % oracle.e_rel(y[i], refs[d][finite.index(i)], bs.x[i])[0])
+                cell.setdefault(name, {})[d] = entry
+        diag[str(n)] = cell
+    out["boundary_diagnostics"] = diag
+    log("scored everything")
+    return summary
 
 
 if __name__ == "__main__":

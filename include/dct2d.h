@@ -122,8 +122,9 @@ int dct2d_roundtrip(float* data, int64_t batch, int32_t rows, int32_t cols, int6
                     void* stream);
 
 /* General entry: direction `dir` (DCT2D_FORWARD/INVERSE/ROUNDTRIP), out-of-place or
- * in-place (in == out allowed; partially overlapping buffers are not), explicit
- * arithmetic path `precision` (dct2d_precision).  in_stride / out_stride as above.
+ * in-place (in == out allowed, with in_stride == out_stride when batch > 1; partially
+ * overlapping buffers are not: DCT2D_ERR_ARG), explicit arithmetic path `precision`
+ * (dct2d_precision).  in_stride / out_stride as above.
  * Returns DCT2D_ERR_PRECISION when the path does not exist for the size. */
 int dct2d_transform_ex(int dir, const float* in, float* out, int64_t batch, int32_t rows,
                        int32_t cols, int64_t in_stride, int64_t out_stride, int precision,
@@ -200,8 +201,15 @@ int dct2d_ragged_plan_info(const dct2d_ragged_plan* plan, int64_t* items, int32_
  * "variant" chosen by the autotuner ahead of time and frozen (Section 3.2: variants
  * fixed per size and direction before measurement).  dct2d_tune measures the
  * candidate variants for one case on scratch data it allocates itself (call it
- * outside timed regions) and freezes the fastest one that passes the library's own
- * self-consistency check; dct2d_get_variant / dct2d_set_variant read and override the
+ * outside timed regions) and freezes the fastest one that passes a correctness
+ * guard which trusts no other candidate: on 48 arrays spread over the whole batch
+ * (first and last included) the candidate composed with the opposite transform must
+ * return its input (round trip: its own output; forward / inverse: followed by the
+ * frozen float32 inverse / forward; filter: multipliers 1 and -1/2 must give X and
+ * -X/2) within the round-trip gate 4e-6 (float32-accurate paths) or a bound above
+ * the path's error band (single-pass and BF16X3).  A candidate that fails is never
+ * frozen; if every candidate fails, dct2d_tune returns DCT2D_ERR_HIP and leaves the
+ * table unchanged.  dct2d_get_variant / dct2d_set_variant read and override the
  * frozen table; dct2d_variant_count gives the number of candidates (0 = none).
  * `dir` may also be DCT2D_FILTER, with precision DCT2D_FP32 (or DCT2D_AUTO, which for the
  * filter always means DCT2D_FP32): the filter's own frozen variant, which starts as the
@@ -211,6 +219,15 @@ int dct2d_get_variant(int32_t rows, int32_t cols, int dir, int precision);
 int dct2d_set_variant(int32_t rows, int32_t cols, int dir, int precision, int variant);
 int dct2d_tune(int32_t rows, int32_t cols, int dir, int precision, int64_t batch, void* stream,
                float* best_ms);
+
+/* ---- measurement reference -------------------------------------------------------
+ * Copies n float32 values from `in` to `out` (device pointers, 16-byte aligned; in ==
+ * out allowed, partial overlap is not) with a plain streaming kernel: one read and one
+ * write per element, the same algorithmic traffic as a transform.  Not a transform:
+ * it is the practical HBM ceiling the benchmark times in the same run (the transforms'
+ * achieved GB/s is reported against it as well as against the 8 TB/s peak).
+ * Errors: DCT2D_ERR_ARG (n < 0, null pointer with n > 0, overlap), DCT2D_ERR_ALIGN. */
+int dct2d_copy(const float* in, float* out, int64_t n, void* stream);
 
 /* Human-readable text for a status code (static storage). */
 const char* dct2d_status_string(int status);

@@ -27,7 +27,8 @@ DIRECTIONS = {"forward": FORWARD, "inverse": INVERSE, "roundtrip": ROUNDTRIP, "f
 EXPORTS = ("dct2d_init", "dct2d_finalize", "dct2d_forward", "dct2d_inverse", "dct2d_roundtrip",
            "dct2d_transform_ex", "dct2d_filter", "dct2d_ragged_plan_create", "dct2d_ragged_execute",
            "dct2d_ragged_plan_destroy", "dct2d_ragged_plan_info", "dct2d_variant_count",
-           "dct2d_get_variant", "dct2d_set_variant", "dct2d_tune", "dct2d_status_string", "dct2d_version")
+           "dct2d_get_variant", "dct2d_set_variant", "dct2d_tune", "dct2d_status_string", "dct2d_version",
+           "dct2d_copy")
 
 
 class DCT2DError(RuntimeError):
@@ -69,6 +70,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         getattr(lib, n).argtypes = [i32, i32, c_int, c_int]
     lib.dct2d_set_variant.argtypes = [i32, i32, c_int, c_int, c_int]
     lib.dct2d_tune.argtypes = [i32, i32, c_int, c_int, i64, vp, ctypes.POINTER(ctypes.c_float)]
+    lib.dct2d_copy.argtypes = [vp, vp, i64, vp]
     lib.dct2d_status_string.argtypes = [c_int]
     lib.dct2d_status_string.restype = ctypes.c_char_p
     lib.dct2d_version.argtypes = []
@@ -122,6 +124,18 @@ def _geometry(t, rows, cols, stride, batch=None):
     return int(batch), int(rows), int(cols), int(stride)
 
 
+def _check_out(inp, out):
+    """The output must be a contiguous float32 tensor with the input's shape on the input's device:
+    the C ABI receives a raw device pointer and cannot tell a host or differently typed buffer apart."""
+    import torch
+    if out.dtype != torch.float32:
+        raise TypeError("out must be float32")
+    if not out.is_cuda or out.device != inp.device:
+        raise TypeError("out must be a CUDA (HIP) tensor on the input's device")
+    if out.shape != inp.shape or not out.is_contiguous():
+        raise ValueError("out must be contiguous with the input's shape")
+
+
 def _inplace(name, t, rows, cols, stride, stream, batch=None):
     batch, rows, cols, stride = _geometry(t, rows, cols, stride, batch)
     fn = getattr(load(), name)
@@ -152,8 +166,7 @@ def transform(inp, out=None, direction="forward", precision="auto", stream=None)
     d = DIRECTIONS[direction] if isinstance(direction, str) else int(direction)
     p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     batch, rows, cols, stride = _geometry(inp, None, None, None)
-    if out.shape != inp.shape or not out.is_contiguous():
-        raise ValueError("out must be contiguous with the input's shape")
+    _check_out(inp, out)
     rc = load().dct2d_transform_ex(d, ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()), batch,
                                    rows, cols, stride, stride, p, ctypes.c_void_p(_stream(stream)))
     _check(rc, "dct2d_transform_ex")
@@ -168,10 +181,9 @@ def filter(inp, lam, out=None, stream=None):
     if out is None:
         out = torch.empty_like(inp)
     batch, rows, cols, stride = _geometry(inp, None, None, None)
-    if out.shape != inp.shape or not out.is_contiguous():
-        raise ValueError("out must be contiguous with the input's shape")
-    if lam.dtype != torch.float32 or not lam.is_cuda or not lam.is_contiguous():
-        raise TypeError("lam must be a contiguous float32 CUDA tensor")
+    _check_out(inp, out)
+    if lam.dtype != torch.float32 or not lam.is_cuda or not lam.is_contiguous() or lam.device != inp.device:
+        raise TypeError("lam must be a contiguous float32 CUDA tensor on the input's device")
     if tuple(lam.shape) == (rows, cols):
         lam_stride = 0
     elif lam.shape == inp.shape:
@@ -182,6 +194,20 @@ def filter(inp, lam, out=None, stream=None):
                              stride, stride, ctypes.c_void_p(lam.data_ptr()), lam_stride,
                              ctypes.c_void_p(_stream(stream)))
     _check(rc, "dct2d_filter")
+    return out
+
+
+def copy(inp, out=None, stream=None):
+    """Plain device copy through the library's reference streaming kernel (dct2d_copy): the
+    practical HBM ceiling of a one-read-one-write kernel.  out may be inp."""
+    import torch
+    if out is None:
+        out = torch.empty_like(inp)
+    if inp.dtype != torch.float32 or not inp.is_cuda or not inp.is_contiguous():
+        raise TypeError("contiguous float32 CUDA tensor required")
+    _check_out(inp, out)
+    _check(load().dct2d_copy(ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()), inp.numel(),
+                             ctypes.c_void_p(_stream(stream))), "dct2d_copy")
     return out
 
 
@@ -260,10 +286,24 @@ class RaggedPlan:
         h = ctypes.c_void_p()
         d = DIRECTIONS[direction] if isinstance(direction, str) else int(direction)
         p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self._h = None
         _check(load().dct2d_ragged_plan_create(arr, n, d, p, ctypes.byref(h)), "dct2d_ragged_plan_create")
         self._h = h
+        # floats a base buffer must hold: the end of the furthest array of the plan
+        self.extent = max(int(offsets[i]) + int(rows[i]) * int(cols[i]) for i in range(n))
+        import torch
+        self.device = torch.device("cuda", torch.cuda.current_device())
 
     def execute(self, base, stream=None):
+        """Runs the plan in place on the arrays of `base` (a contiguous float32 tensor on the
+        plan's device holding at least `extent` floats)."""
+        import torch
+        if base.dtype != torch.float32 or not base.is_cuda or base.device != self.device:
+            raise TypeError("base must be a float32 CUDA tensor on the plan's device (%s)" % self.device)
+        if not base.is_contiguous():
+            raise ValueError("base must be contiguous (arrays are addressed from its first element)")
+        if base.numel() < self.extent:
+            raise ValueError("base holds %d floats, the plan addresses %d" % (base.numel(), self.extent))
         _check(load().dct2d_ragged_execute(self._h, ctypes.c_void_p(base.data_ptr()),
                                            ctypes.c_void_p(_stream(stream))), "dct2d_ragged_execute")
         return base

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -91,7 +92,11 @@ int validate(int dir, const float* in, const float* out, int64_t batch, int32_t 
     if (batch == 0) return DCT2D_OK;
     if (!in || !out) return DCT2D_ERR_ARG;
     if (!aligned16(in) || !aligned16(out) || (in_stride & 3) || (out_stride & 3)) return DCT2D_ERR_ALIGN;
-    if (in != out) {
+    if (in == out) {
+        // in place means array b is read and written at the same place; with different
+        // strides array b's output would land on another array's input
+        if (batch > 1 && in_stride != out_stride) return DCT2D_ERR_ARG;
+    } else {
         // partially overlapping buffers are not supported
         const char* a0 = reinterpret_cast<const char*>(in);
         const char* a1 = a0 + ((batch - 1) * in_stride + n) * 4;
@@ -119,6 +124,28 @@ int variant_count(int rows, int cols, int dir, int prec)
     if (dir == DIR_FILTER) return 0; // the filter exists on the float32 path only
     if (!mfma_supported(rows, cols, prec)) return 0;
     return mfma_variant_count(rows, cols, dir, prec);
+}
+
+// Arrays per candidate that the tuner's correctness guard reads back.
+constexpr int64_t kTuneSamples = 48;
+
+// Largest sampled relative error the guard accepts per path: the round-trip gate for the
+// float32-accurate paths, a bound well above the measured error band for the others.
+double tune_tolerance(int prec)
+{
+    switch (prec) {
+    case DCT2D_SPLIT_BF16X3: return 1e-4;
+    case DCT2D_BF16: return 5e-2;
+    case DCT2D_FP16: return 1e-2;
+    case DCT2D_FP8_E4M3: return 0.5;
+    default: return 4e-6;
+    }
+}
+
+__global__ void k_const(float* p, int64_t n, float v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // Deterministic scratch fill for tuning: a counter hash mapped to [-1, 1).
@@ -287,43 +314,86 @@ int dct2d_tune(int32_t rows, int32_t cols, int dir, int precision, int64_t batch
     const DeviceTables* t = tables_current(&rc);
     if (!t) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t n = batch * rows * cols;
-    float *src = nullptr, *dst = nullptr, *ref = nullptr, *lam = nullptr;
-    const int64_t nl = dir == DCT2D_FILTER ? (int64_t)rows * cols : 0; // one shared multiplier array
-    if (hipMalloc(&src, (n + nl) * 4) != hipSuccess) return DCT2D_ERR_NOMEM;
+    const int64_t per = (int64_t)rows * cols;
+    const int64_t n = batch * per;
+    // scratch: input, candidate output, and the back-transform that checks it; for the
+    // filter the last rows*cols floats of `chk` hold a constant multiplier array
+    float *src = nullptr, *dst = nullptr, *chk = nullptr;
+    if (hipMalloc(&src, n * 4) != hipSuccess) return DCT2D_ERR_NOMEM;
     if (hipMalloc(&dst, n * 4) != hipSuccess) { hipFree(src); return DCT2D_ERR_NOMEM; }
-    if (hipMalloc(&ref, n * 4) != hipSuccess) { hipFree(src); hipFree(dst); return DCT2D_ERR_NOMEM; }
-    k_fill<<<(unsigned)((n + nl + 255) / 256), 256, 0, s>>>(src, n + nl, 0x5eedu);
-    if (nl) lam = src + n;
+    if (hipMalloc(&chk, (n + per) * 4) != hipSuccess) { hipFree(src); hipFree(dst); return DCT2D_ERR_NOMEM; }
+    float* lam = chk + n;
+    k_fill<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(src, n, 0x5eedu);
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
-    std::vector<float> host_ref, host_out;
+    // arrays checked per candidate: spread evenly over the whole batch, first and last
+    // included, so every pass of a grid-stride or persistent schedule is seen
+    const int64_t ns = batch < kTuneSamples ? batch : kTuneSamples;
+    std::vector<int64_t> sample((size_t)ns);
+    for (int64_t i = 0; i < ns; ++i) sample[(size_t)i] = ns == 1 ? 0 : i * (batch - 1) / (ns - 1);
+    std::vector<float> h_in((size_t)(ns * per)), h_out((size_t)(ns * per));
+    auto fetch = [&](const float* dev, std::vector<float>& host) {
+        for (int64_t i = 0; i < ns; ++i)
+            if (hipMemcpy(host.data() + i * per, dev + sample[(size_t)i] * per, per * 4, hipMemcpyDeviceToHost) !=
+                hipSuccess)
+                return false;
+        return true;
+    };
+    // max over the sampled arrays of ||out_b - c in_b|| / ||in_b||
+    auto worst = [&](float c) {
+        double w = 0.0;
+        for (int64_t i = 0; i < ns; ++i) {
+            double num = 0, den = 0;
+            for (int64_t k = 0; k < per; ++k) {
+                const double a = h_in[(size_t)(i * per + k)], b = h_out[(size_t)(i * per + k)];
+                num += (b - c * a) * (b - c * a);
+                den += a * a;
+            }
+            const double e = den > 0 ? std::sqrt(num / den) : std::sqrt(num);
+            if (!(e <= w)) w = e; // NaN propagates as a failure
+        }
+        return w;
+    };
+    const double tol = tune_tolerance(precision);
+    if (!fetch(src, h_in)) rc = DCT2D_ERR_HIP;
     int best = -1;
     float best_t = 0.f;
     for (int v = 0; v < nv && rc == DCT2D_OK; ++v) {
-        Job j{dir, src, v == 0 ? ref : dst, batch, rows, cols, rows * (int64_t)cols, rows * (int64_t)cols, s, v};
-        j.lam = lam;
-        auto launch = [&]() {
-            return precision == DCT2D_FP32 ? launch_fp32(t, j) : launch_mfma(t, j, precision);
-        };
-        if ((rc = launch()) != DCT2D_OK) break;
-        if (hipStreamSynchronize(s) != hipSuccess) { rc = DCT2D_ERR_HIP; break; }
-        // self-consistency: every variant must agree with variant 0 to float32 accuracy
-        if (v > 0) {
-            const int64_t m = n < (1 << 20) ? n : (1 << 20);
-            host_ref.resize(m);
-            host_out.resize(m);
-            hipMemcpy(host_ref.data(), ref, m * 4, hipMemcpyDeviceToHost);
-            hipMemcpy(host_out.data(), dst, m * 4, hipMemcpyDeviceToHost);
-            double num = 0, den = 0;
-            for (int64_t i = 0; i < m; ++i) {
-                const double d = (double)host_out[i] - host_ref[i];
-                num += d * d;
-                den += (double)host_ref[i] * host_ref[i];
+        Job j{dir, src, dst, batch, rows, cols, per, per, s, v};
+        j.lam = dir == DCT2D_FILTER ? lam : nullptr;
+        auto launch = [&]() { return precision == DCT2D_FP32 ? launch_fp32(t, j) : launch_mfma(t, j, precision); };
+        // Correctness guard, independent of every other candidate: the candidate's
+        // composition with the opposite transform must return the input.  Round trip:
+        // its own output.  Filter: multipliers 1 (identity) and -1/2 (-X/2).  Forward and
+        // inverse: followed by the frozen float32 inverse / forward; a wrong candidate
+        // cannot be cancelled by a correct partner.
+        bool ok = true;
+        const int checks = dir == DCT2D_FILTER ? 2 : 1;
+        for (int c = 0; c < checks && ok && rc == DCT2D_OK; ++c) {
+            const float lam_c = c == 0 ? 1.0f : -0.5f;
+            if (dir == DCT2D_FILTER) {
+                k_const<<<(unsigned)((per + 255) / 256), 256, 0, s>>>(lam, per, lam_c);
+                if (hipGetLastError() != hipSuccess) { rc = DCT2D_ERR_HIP; break; }
             }
-            if (den > 0 && num > 1e-10 * den) continue; // disagrees: never selected
+            if ((rc = launch()) != DCT2D_OK) break;
+            const float* res = dst;
+            if (dir == DCT2D_FORWARD || dir == DCT2D_INVERSE) {
+                Job back{dir == DCT2D_FORWARD ? DCT2D_INVERSE : DCT2D_FORWARD, dst, chk, batch, rows, cols, per, per,
+                         s, variant_for(rows, cols, dir == DCT2D_FORWARD ? DCT2D_INVERSE : DCT2D_FORWARD,
+                                        DCT2D_FP32)};
+                if ((rc = launch_fp32(t, back)) != DCT2D_OK) break;
+                res = chk;
+            }
+            if (hipStreamSynchronize(s) != hipSuccess || !fetch(res, h_out)) { rc = DCT2D_ERR_HIP; break; }
+            ok = worst(dir == DCT2D_FILTER ? lam_c : 1.0f) <= tol;
         }
+        if (rc != DCT2D_OK) break;
+        if (!ok) continue; // fails the identity: never selected
+        if (dir == DCT2D_FILTER) {
+            k_fill<<<(unsigned)((per + 255) / 256), 256, 0, s>>>(lam, per, 0x1a3bu); // timing multipliers
+        }
+        if ((rc = launch()) != DCT2D_OK) break; // warm
         float ms = 0.f;
         const int reps = 5;
         hipEventRecord(e0, s);
@@ -339,9 +409,10 @@ int dct2d_tune(int32_t rows, int32_t cols, int dir, int precision, int64_t batch
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    hipStreamSynchronize(s);
     hipFree(src);
     hipFree(dst);
-    hipFree(ref);
+    hipFree(chk);
     if (rc != DCT2D_OK) return rc;
     if (best < 0) return DCT2D_ERR_HIP;
     if (best_ms) *best_ms = best_t;

@@ -1,0 +1,54 @@
+// The library's reference copy: the practical HBM ceiling of a kernel that reads each
+// float32 element once and writes it once, as every transform here does.  Measured on
+// MI355X over 512 MiB (sweep of tile size, workgroup size and resident workgroups per
+// CU): 256-thread workgroups that each move one 4 KiB tile (one 16-byte chunk per
+// lane, consecutive lanes on consecutive chunks), one tile per workgroup, reach
+// 6.2 TB/s out of place; larger tiles per workgroup or fewer resident workgroups are
+// slower.  The transforms are compared against this kernel timed in the same run.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace {
+
+constexpr int kCopyThreads = 256;
+
+__global__ void __launch_bounds__(kCopyThreads) k_copy(const float4* in, float4* out, int64_t n4)
+{
+    const int64_t k = (int64_t)blockIdx.x * kCopyThreads + threadIdx.x;
+    if (k < n4) ((dct::gfloat4*)out)[k] = ((const dct::gfloat4*)in)[k];
+}
+
+__global__ void __launch_bounds__(64) k_copy_tail(const float* in, float* out, int64_t from, int64_t n)
+{
+    const int64_t k = from + threadIdx.x;
+    if (k < n) ((dct::gfloat*)out)[k] = ((const dct::gfloat*)in)[k];
+}
+
+} // namespace
+
+extern "C" int dct2d_copy(const float* in, float* out, int64_t n, void* stream)
+{
+    if (n < 0) return DCT2D_ERR_ARG;
+    if (n == 0) return DCT2D_OK;
+    if (!in || !out) return DCT2D_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(in) & 15u) || (reinterpret_cast<uintptr_t>(out) & 15u)) return DCT2D_ERR_ALIGN;
+    if (in != out) {
+        const char* a0 = reinterpret_cast<const char*>(in);
+        const char* b0 = reinterpret_cast<const char*>(out);
+        if (a0 < b0 + n * 4 && b0 < a0 + n * 4) return DCT2D_ERR_ARG;
+    }
+    int rc = DCT2D_OK;
+    if (!dct::tables_current(&rc)) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n4 = n / 4;
+    if (n4 > 0) {
+        const int64_t grid = (n4 + kCopyThreads - 1) / kCopyThreads;
+        if (grid > 0x7fffffff) return DCT2D_ERR_ARG;
+        k_copy<<<(unsigned)grid, kCopyThreads, 0, s>>>(reinterpret_cast<const float4*>(in),
+                                                       reinterpret_cast<float4*>(out), n4);
+    }
+    if (n4 * 4 < n)
+        k_copy_tail<<<1, 64, 0, s>>>(in, out, n4 * 4, n);
+    return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
+}

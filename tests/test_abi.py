@@ -51,6 +51,9 @@ def test_argument_validation_on_host():
     assert lib.dct2d_forward(None, 3, 8, 8, 64, None) == -1           # null data with batch > 0
     assert lib.dct2d_forward(ctypes.c_void_p(0x1004), 3, 8, 8, 64, None) == -4   # misaligned
     assert lib.dct2d_forward(ctypes.c_void_p(0x1000), 3, 8, 8, 66, None) == -4   # stride % 4
+    # in place (in == out) with different strides: array b would land on another array's input
+    assert lib.dct2d_transform_ex(0, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1000), 3, 8, 8, 80, 64, 0,
+                                  None) == -1
     # overlapping out-of-place buffers
     assert lib.dct2d_transform_ex(0, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1100), 4, 8, 8, 64, 64, 0,
                                   None) == -1

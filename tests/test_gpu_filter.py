@@ -169,26 +169,41 @@ def test_batch_zero_and_argument_errors():
 
 @pytest.mark.parametrize("n", (8, 16, 32, 64, 128, 256))
 def test_filter_full_size_sampled(n):
-    """512 MiB batch (2^27/N^2 arrays of N(0,1)), in place, one shared Poisson operator, as the
-    benchmark times it; 96 sampled arrays (first, last, random) checked against the oracle."""
+    """512 MiB batch (2^27/N^2 arrays of N(0,1)), one shared Poisson operator, as the benchmark
+    times it (in place), and at N = 128 and 256 also in every variant whose workgroups loop over
+    several arrays; about 160 arrays spread over the whole batch (one per segment, the first and
+    the last among them, so every pass of a loop) are checked against the oracle."""
     import torch
     import workloads
+    from tests.gpu_util import spread
     dct = _lib()
     bt = workloads.c3_normal(n)
     batch = bt.x.shape[0]
-    g = np.random.default_rng(n + 1)
-    idx = np.unique(np.concatenate([[0, batch - 1], g.integers(0, batch, 94)]))
+    idx = spread(batch, 160, seed=n + 1)
     xs = bt.x[idx].copy()
-    t = to_gpu(bt.x)
+    x_dev = to_gpu(bt.x)
     del bt
     lam = poisson_multipliers(n, n)
-    dct.filter(t, to_gpu(lam), out=t)
-    torch.cuda.synchronize()
-    y = t[torch.from_numpy(idx).cuda()].cpu().numpy()
-    del t
+    lam_dev = to_gpu(lam)
+    sel = torch.from_numpy(idx).cuda()
+    keep = dct.get_variant(n, n, "filter", "fp32")
+    variants = {128: (None, 0, 3), 256: (None, 0, 2, 3, 4)}.get(n, (None,))
+    try:
+        for v in variants:
+            if v is not None:
+                dct.set_variant(n, n, "filter", "fp32", v)
+            t = x_dev.clone()
+            dct.filter(t, lam_dev, out=t)
+            torch.cuda.synchronize()
+            y = t[sel].cpu().numpy()
+            del t
+            e = _score(xs, y, lam)
+            assert np.isfinite(e).all() and e.max() <= GATE, "N=%d variant %s: %.3e at array %d" % (
+                n, "frozen" if v is None else v, e.max(), idx[int(np.argmax(e))])
+    finally:
+        dct.set_variant(n, n, "filter", "fp32", keep)
+    del x_dev
     torch.cuda.empty_cache()
-    e = _score(xs, y, lam)
-    assert np.isfinite(e).all() and e.max() <= GATE, "N=%d: %.3e" % (n, e.max())
 
 
 @pytest.mark.parametrize("h,w", ((8, 8), (32, 16), (64, 64), (128, 128), (256, 256), (8, 256)))

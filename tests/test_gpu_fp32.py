@@ -162,30 +162,82 @@ def test_c2_mixture_fp32(direction):
         assert e[bt.category == c].max() <= GATE[direction], "category %d" % c
 
 
+def _full_batch_check(dct, n, x_dev, xs, idx, refs, label, call):
+    """Runs `call(direction, tensor)` on a fresh full-size copy per direction and checks: the
+    sampled arrays against the oracle (forward, inverse: the input read as a spectrum) or the
+    input (round trip); every array of the batch against a closed form that needs no oracle
+    (round trip: the input itself; forward and inverse: Parseval's norm identity)."""
+    import torch
+    from tests.gpu_util import parseval_rel, per_array_rel
+    sel = torch.from_numpy(idx).cuda()
+    for d in DIRS:
+        t = x_dev.clone()
+        call(d, t)
+        torch.cuda.synchronize()
+        y = t[sel].cpu().numpy()
+        e = oracle.e_rel(y, refs[d], xs)
+        assert np.isfinite(e).all() and e.max() <= GATE[d], "%s %s: sampled max e_rel %.3e at array %d" % (
+            label, d, e.max(), idx[int(np.argmax(e))])
+        if d == "roundtrip":
+            whole = per_array_rel(t, x_dev)
+            gate = GATE[d]
+        else:
+            whole = parseval_rel(t, x_dev)
+            gate = GATE[d]
+        assert np.isfinite(whole).all() and whole.max() <= gate, "%s %s: array %d off by %.3e (all %d arrays)" % (
+            label, d, int(np.argmax(whole)), whole.max(), whole.size)
+        del t
+    torch.cuda.empty_cache()
+
+
+def _sample_refs(xs):
+    return {"forward": oracle.forward(xs), "inverse": oracle.inverse(xs), "roundtrip": xs.astype(np.float64)}
+
+
 @pytest.mark.parametrize("n", SIZES)
 def test_full_size_c3_sampled(n):
-    """Full 512 MiB batch (2^27/N^2 arrays of N(0,1)), in place, in the launch configuration the
-    benchmark times; 192 sampled arrays (first, last, random) checked against the oracle."""
-    import torch
-    import paper_2609_28519_amd as dct
-    _lib()
+    """Full 512 MiB batch (2^27/N^2 arrays of N(0,1)), in place through the three basic calls
+    (forward_, inverse_ and the fused roundtrip_), in the launch configuration the benchmark
+    times.  About 200 arrays spread over the whole batch (one per segment, the first and the last
+    among them) are checked against the oracle; every array is checked against a closed form."""
+    from tests.gpu_util import spread
+    dct = _lib()
     bt = workloads.c3_normal(n)
     batch = bt.x.shape[0]
-    g = np.random.default_rng(n)
-    idx = np.unique(np.concatenate([[0, batch - 1], g.integers(0, batch, 190)]))
+    idx = spread(batch, 200, seed=n)
     xs = bt.x[idx].copy()
-    t = to_gpu(bt.x)
+    x_dev = to_gpu(bt.x)
     del bt
-    dct.forward_(t)
-    torch.cuda.synchronize()
-    y = t[torch.from_numpy(idx).cuda()].cpu().numpy()
-    assert_parity(xs, y, "forward", label="full N=%d" % n)
-    dct.inverse_(t)
-    torch.cuda.synchronize()
-    y2 = t[torch.from_numpy(idx).cuda()].cpu().numpy()
-    assert oracle.e_rel(y2, xs, xs).max() <= GATE["roundtrip"]
-    del t
-    torch.cuda.empty_cache()
+    calls = {"forward": dct.forward_, "inverse": dct.inverse_, "roundtrip": dct.roundtrip_}
+    _full_batch_check(dct, n, x_dev, xs, idx, _sample_refs(xs), "full N=%d" % n, lambda d, t: calls[d](t))
+
+
+@pytest.mark.parametrize("n,variants", [(256, (0, 1, 2, 3, 4)), (128, (0, 3, 4, 5))])
+def test_full_batch_every_looping_variant(n, variants):
+    """The variants whose workgroups loop over several arrays (N = 256: one resident workgroup per
+    CU walks about eight arrays; N = 128 variants 0 and 3: grid-stride loops), and their
+    one-array-per-workgroup siblings, at the full 512 MiB batch, every direction, in place:
+    arrays from every pass of each loop are checked against the oracle, and every array against
+    its closed form."""
+    from tests.gpu_util import spread
+    dct = _lib()
+    bt = workloads.c3_normal(n, seed=4321 + n)
+    batch = bt.x.shape[0]
+    idx = spread(batch, 160, seed=7 * n)
+    xs = bt.x[idx].copy()
+    refs = _sample_refs(xs)
+    x_dev = to_gpu(bt.x)
+    del bt
+    keep = {d: dct.get_variant(n, n, d, "fp32") for d in DIRS}
+    try:
+        for v in variants:
+            for d in DIRS:
+                dct.set_variant(n, n, d, "fp32", v)
+            _full_batch_check(dct, n, x_dev, xs, idx, refs, "N=%d v%d" % (n, v),
+                              lambda d, t: dct.transform(t, t, d, "fp32"))
+    finally:
+        for d in DIRS:
+            dct.set_variant(n, n, d, "fp32", keep[d])
 
 
 @pytest.mark.parametrize("h,w", [(8, 8), (16, 16), (32, 32), (64, 64), (128, 128), (256, 256), (8, 64), (64, 16),

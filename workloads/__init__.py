@@ -188,3 +188,23 @@ def c5_ladder(n: int, batch: int = 1 << 18, seed: int | None = None) -> Batch:
         out[idx] = blk.astype(np.float32)
     weak[iw] = kl
     return Batch(out, cat, weak)
+
+
+BOUNDARY_CASES = ("normal", "subnormal", "large", "impulse_3e38", "nan", "inf")
+
+
+def boundary_set(n: int, seed: int = SEED_BASE + 6) -> Batch:
+    """Boundary diagnostics (Section 6: subnormals, extreme finite amplitudes), one n x n array per
+    case, in the order of BOUNDARY_CASES: U[-1,1]; U[-1,1] * 1e-40 (subnormal float32); U[-1,1] *
+    FLT_MAX / n, whose exact orthonormal transform is still representable (its Frobenius norm is at
+    most FLT_MAX / sqrt(3)) while unnormalised intermediate sums need not be; a single impulse of
+    3e38; U[-1,1] with one NaN; U[-1,1] with one +Inf."""
+    g = rng(seed + n)
+    x = g.uniform(-1.0, 1.0, size=(len(BOUNDARY_CASES), n, n))
+    x[1] *= 1e-40
+    x[2] *= float(np.finfo(np.float32).max) / n
+    x[3] = 0.0
+    x[3, n // 3, n // 5] = 3e38
+    x[4, n // 3, n // 5] = np.nan
+    x[5, n // 2, 1] = np.inf
+    return Batch(x.astype(np.float32), np.arange(len(BOUNDARY_CASES), dtype=np.int8))
