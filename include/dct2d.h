@@ -155,6 +155,25 @@ int dct2d_filter(const float* in, float* out, int64_t batch, int32_t rows, int32
                  int64_t in_stride, int64_t out_stride, const float* lambda, int64_t lambda_stride,
                  void* stream);
 
+/* ---- whole images of any shape ----------------------------------------------------------
+ * Batched transform (direction as dct2d_transform_ex) of `batch` images of rows x cols with
+ * both axes in [8, 1024] and cols a multiple of 4, including lengths that are not powers of
+ * two (384, 600, 1000, ...): the strided-batch form of the ragged planner's image classes.
+ * Pointers, strides, alignment and in-place rules as dct2d_transform_ex.  Shapes with both
+ * axes powers of two up to 256 run the basic calls' kernels (DCT2D_AUTO).  Every other shape
+ * is computed exactly from the dense Q_n of eq. 1 (Section 2.1; the paper's own library
+ * rejects non-power-of-two axes, Section 7.1, rather than zero-padding them, which would
+ * change the transform): one dense float32 product per axis (two for the round trip), with
+ * the top even/odd level of Q_n's symmetry taken out where n is a multiple of 8.  The passes
+ * go through a workspace of rows*cols floats per image (batch images, at most 65535 at a
+ * time), taken from the stream-ordered allocator on `stream` and released on it; the dense
+ * Q_n of each length is built once per device on first use (so the first call of a shape
+ * synchronises the device) and kept until dct2d_finalize.
+ * Errors: DCT2D_ERR_SIZE (shape), DCT2D_ERR_NOMEM (workspace), as dct2d_transform_ex
+ * otherwise. */
+int dct2d_image_transform(int dir, const float* in, float* out, int64_t batch, int32_t rows,
+                          int32_t cols, int64_t in_stride, int64_t out_stride, void* stream);
+
 /* ---- ragged batches: many arrays of different shapes in one launch ------------------
  * A descriptor names one array inside a caller buffer: its first element is at
  * base + offset (floats), its shape rows x cols (pitch = cols).  Arrays must not

@@ -187,7 +187,11 @@ int dct2d_init(int device)
     return DCT2D_OK;
 }
 
-void dct2d_finalize(void) { tables_release_all(); }
+void dct2d_finalize(void)
+{
+    image_release_all();
+    tables_release_all();
+}
 
 int dct2d_forward(float* data, int64_t batch, int32_t rows, int32_t cols, int64_t stride, void* stream)
 {

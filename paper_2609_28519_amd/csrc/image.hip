@@ -1,0 +1,147 @@
+// Batched transforms of whole images of any shape with both axes in [8, 1024] (columns a
+// multiple of 4): the strided-batch counterpart of the ragged planner's image classes.
+//
+// Shapes whose axes are both powers of two up to 256 go to the fast kernels of the basic
+// calls (the frozen float32-accurate path).  Every other shape (512, 1024, and axes that
+// are not powers of two, such as 384 or 600) is computed exactly from the dense Q_n of
+// eq. 1 (FP64-generated, rounded to float32; no zero-padding), one dense product per axis
+// (kern_dense.hip).  A dense pass writes its output tile from whole input rows or
+// columns, so the two (round trip: four) passes ping-pong through a workspace of one
+// float32 image per image of the batch:
+//   forward / inverse   in -> ws (row pass, Q_cols)       ws -> out (column pass, Q_rows)
+//   round trip          in -> ws -> out (forward)          out -> ws -> out (inverse)
+//
+// dct2d_image_transform takes its workspace from the stream-ordered allocator
+// (hipMallocAsync / hipFreeAsync on the caller's stream, so concurrent calls on different
+// streams never share it) and keeps one dense Q_n per device and length, built on first
+// use.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "internal.hpp"
+
+using namespace dct;
+
+namespace {
+
+std::mutex g_mu;
+// dense Q_n cache of the allocating entry point: (device, n) -> device table
+std::map<std::pair<int, int>, float*> g_q;
+
+bool fast_shape(int r, int c) { return is_pow2(r) && is_pow2(c) && r >= 8 && r <= 256 && c >= 8 && c <= 256; }
+
+int validate(int dir, const float* in, const float* out, int64_t batch, int rows, int cols, int64_t in_stride,
+             int64_t out_stride)
+{
+    if (dir < DCT2D_FORWARD || dir > DCT2D_ROUNDTRIP || batch < 0) return DCT2D_ERR_ARG;
+    if (rows < 8 || cols < 8 || rows > 1024 || cols > 1024 || (cols & 3)) return DCT2D_ERR_SIZE;
+    const int64_t n = (int64_t)rows * cols;
+    if (in_stride < n || out_stride < n) return DCT2D_ERR_STRIDE;
+    if (batch == 0) return DCT2D_OK;
+    if (!in || !out) return DCT2D_ERR_ARG;
+    if ((reinterpret_cast<uintptr_t>(in) & 15u) || (reinterpret_cast<uintptr_t>(out) & 15u) || (in_stride & 3) ||
+        (out_stride & 3))
+        return DCT2D_ERR_ALIGN;
+    if (in == out) {
+        if (batch > 1 && in_stride != out_stride) return DCT2D_ERR_ARG;
+    } else {
+        const char* a0 = reinterpret_cast<const char*>(in);
+        const char* a1 = a0 + ((batch - 1) * in_stride + n) * 4;
+        const char* b0 = reinterpret_cast<const char*>(out);
+        const char* b1 = b0 + ((batch - 1) * out_stride + n) * 4;
+        if (a0 < b1 && b0 < a1) return DCT2D_ERR_ARG;
+    }
+    return DCT2D_OK;
+}
+
+// The dense passes of `count` images (count <= 65535, the grid's z extent): in and out
+// strided, the workspace packed (rows * cols floats per image).
+int dense_passes(int dir, const float* in, float* out, int64_t count, int rows, int cols, int64_t in_stride,
+                 int64_t out_stride, const float* q_rows, const float* q_cols, float* ws, hipStream_t s)
+{
+    const int64_t n = (int64_t)rows * cols;
+    const Addr in_ws{in, ws, in_stride, n, nullptr, nullptr, nullptr, nullptr};
+    const Addr ws_out{ws, out, n, out_stride, nullptr, nullptr, nullptr, nullptr};
+    const Addr out_ws{out, ws, out_stride, n, nullptr, nullptr, nullptr, nullptr};
+    const bool inv = dir == DCT2D_INVERSE;
+    int rc = launch_dense_axis(in_ws, count, rows, cols, false, inv, q_cols, s);
+    if (rc == DCT2D_OK) rc = launch_dense_axis(ws_out, count, rows, cols, true, inv, q_rows, s);
+    if (dir == DCT2D_ROUNDTRIP) {
+        if (rc == DCT2D_OK) rc = launch_dense_axis(out_ws, count, rows, cols, true, true, q_rows, s);
+        if (rc == DCT2D_OK) rc = launch_dense_axis(ws_out, count, rows, cols, false, true, q_cols, s);
+    }
+    return rc;
+}
+
+// Cached dense Q_n of the current device (allocating entry point only).
+const float* cached_q(int device, int n, int* err)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_q.find({device, n});
+    if (it != g_q.end()) return it->second;
+    float* q = nullptr;
+    if (hipMalloc(&q, (size_t)n * n * sizeof(float)) != hipSuccess) {
+        *err = DCT2D_ERR_NOMEM;
+        return nullptr;
+    }
+    // built on the null stream and completed before first use on any stream
+    if (tables_dense_q(n, q, nullptr) != DCT2D_OK || hipDeviceSynchronize() != hipSuccess) {
+        hipFree(q);
+        *err = DCT2D_ERR_HIP;
+        return nullptr;
+    }
+    g_q[{device, n}] = q;
+    return q;
+}
+
+} // namespace
+
+void dct::image_release_all()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    int prev = 0;
+    hipGetDevice(&prev);
+    for (auto& kv : g_q) {
+        hipSetDevice(kv.first.first);
+        hipDeviceSynchronize();
+        hipFree(kv.second);
+    }
+    g_q.clear();
+    hipSetDevice(prev);
+}
+
+extern "C" {
+
+int dct2d_image_transform(int dir, const float* in, float* out, int64_t batch, int32_t rows, int32_t cols,
+                          int64_t in_stride, int64_t out_stride, void* stream)
+{
+    int rc = validate(dir, in, out, batch, rows, cols, in_stride, out_stride);
+    if (rc != DCT2D_OK || batch == 0) return rc;
+    const DeviceTables* t = tables_current(&rc);
+    if (!t) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (fast_shape(rows, cols)) {
+        Job j{dir, in, out, batch, rows, cols, in_stride, out_stride, s, 0};
+        return dispatch(t, j, DCT2D_AUTO);
+    }
+    const float* q_rows = cached_q(t->device, rows, &rc);
+    const float* q_cols = q_rows ? cached_q(t->device, cols, &rc) : nullptr;
+    if (!q_rows || !q_cols) return rc;
+    const int64_t n = (int64_t)rows * cols;
+    const int64_t per = batch < 65535 ? batch : 65535;
+    float* ws = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void**>(&ws), (size_t)(per * n) * sizeof(float), s) != hipSuccess)
+        return DCT2D_ERR_NOMEM;
+    for (int64_t b0 = 0; b0 < batch && rc == DCT2D_OK; b0 += per) {
+        const int64_t c = batch - b0 < per ? batch - b0 : per;
+        rc = dense_passes(dir, in + b0 * in_stride, out + b0 * out_stride, c, rows, cols, in_stride, out_stride,
+                          q_rows, q_cols, ws, s);
+    }
+    if (hipFreeAsync(ws, s) != hipSuccess && rc == DCT2D_OK) rc = DCT2D_ERR_HIP;
+    return rc;
+}
+
+} // extern "C"

@@ -40,6 +40,12 @@ constexpr int kF8QShift = 8; // fp8 copy of Q is stored scaled by 2^8 (entries i
 const DeviceTables* tables_current(int* err);
 int tables_init_device(int device);
 void tables_release_all();
+// The current device's tables if dct2d_init (or an earlier call) built them, else nullptr
+// with DCT2D_ERR_NOINIT; never allocates.
+const DeviceTables* tables_ready(int* err);
+
+// Whole-image transforms (image.hip): release of the dense Q cache.
+void image_release_all();
 
 // Generates dense float32 Q_n (eq. 1) for an arbitrary n into a device buffer.
 int tables_dense_q(int n, float* dst, hipStream_t s);

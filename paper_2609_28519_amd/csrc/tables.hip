@@ -256,6 +256,18 @@ const DeviceTables* tables_current(int* err)
     return g_tables[dev];
 }
 
+const DeviceTables* tables_ready(int* err)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        if (err) *err = DCT2D_ERR_NOINIT;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_tables[dev] && err) *err = DCT2D_ERR_NOINIT;
+    return g_tables[dev];
+}
+
 void tables_release_all()
 {
     std::lock_guard<std::mutex> lk(g_mu);

@@ -62,6 +62,24 @@ def test_argument_validation_on_host():
     assert lib.dct2d_set_variant(8, 8, 0, 0, 99) == -1
 
 
+def test_image_transform_validation_on_host():
+    """dct2d_image_transform validates shapes and strides before any device work."""
+    lib = dct.load()
+    for fn in (lib.dct2d_image_transform,):
+        assert fn(0, None, None, 0, 600, 1000, 600000, 600000, None) == 0    # batch 0: no-op
+        assert fn(0, None, None, 0, 384, 512, 384 * 512, 384 * 512, None) == 0
+        assert fn(0, None, None, 0, 7, 8, 56, 56, None) == -2                # axis below 8
+        assert fn(0, None, None, 0, 8, 1028, 8 * 1028, 8 * 1028, None) == -2  # axis above 1024
+        assert fn(0, None, None, 0, 8, 10, 80, 80, None) == -2               # cols not a multiple of 4
+        assert fn(0, None, None, 0, 600, 1000, 10, 10, None) == -3           # stride < rows*cols
+        assert fn(3, None, None, 0, 8, 8, 64, 64, None) == -1                # direction
+        assert fn(0, None, None, -1, 8, 8, 64, 64, None) == -1               # batch < 0
+        assert fn(0, None, None, 2, 8, 8, 64, 64, None) == -1                # null with batch > 0
+        a = ctypes.c_void_p(0x1000)
+        assert fn(0, a, a, 3, 600, 1000, 600004, 600000, None) == -1          # in place, unequal strides
+        assert fn(0, ctypes.c_void_p(0x1004), ctypes.c_void_p(0x900000), 2, 8, 8, 64, 64, None) == -4
+
+
 def test_filter_validation_on_host():
     """dct2d_filter rejects bad arguments before any device work (fake device addresses)."""
     lib = dct.load()
