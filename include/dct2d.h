@@ -174,6 +174,22 @@ int dct2d_filter(const float* in, float* out, int64_t batch, int32_t rows, int32
 int dct2d_image_transform(int dir, const float* in, float* out, int64_t batch, int32_t rows,
                           int32_t cols, int64_t in_stride, int64_t out_stride, void* stream);
 
+/* The same transform for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): allocates nothing and
+ * never builds tables itself.  dct2d_init must have been called for the current device
+ * (DCT2D_ERR_NOINIT otherwise).  The dense Q tables and the workspace live in a fixed
+ * 64 MiB device array that the library holds on every device it runs on until the process
+ * ends; the tables are rebuilt in it on `stream` by every call and the batch is processed in
+ * chunks that fit (every accepted shape fits: 1024 x 1024 needs 12 MiB for one image), so
+ * results equal dct2d_image_transform's.  Calls on one device share that array: calls that
+ * overlap in time on one device (different streams, or threads without ordering) race and
+ * give wrong results.  Same arguments and errors as dct2d_image_transform, except that
+ * DCT2D_ERR_SIZE also marks a shape needing more than the 64 MiB (none of the accepted
+ * shapes does). */
+int dct2d_image_transform_noalloc(int dir, const float* in, float* out, int64_t batch,
+                                  int32_t rows, int32_t cols, int64_t in_stride,
+                                  int64_t out_stride, void* stream);
+
 /* ---- ragged batches: many arrays of different shapes in one launch ------------------
  * A descriptor names one array inside a caller buffer: its first element is at
  * base + offset (floats), its shape rows x cols (pitch = cols).  Arrays must not

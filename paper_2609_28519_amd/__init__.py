@@ -28,7 +28,7 @@ EXPORTS = ("dct2d_init", "dct2d_finalize", "dct2d_forward", "dct2d_inverse", "dc
            "dct2d_transform_ex", "dct2d_filter", "dct2d_ragged_plan_create", "dct2d_ragged_execute",
            "dct2d_ragged_plan_destroy", "dct2d_ragged_plan_info", "dct2d_variant_count",
            "dct2d_get_variant", "dct2d_set_variant", "dct2d_tune", "dct2d_status_string", "dct2d_version",
-           "dct2d_copy", "dct2d_image_transform")
+           "dct2d_copy", "dct2d_image_transform", "dct2d_image_transform_noalloc")
 
 
 class DCT2DError(RuntimeError):
@@ -71,7 +71,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dct2d_set_variant.argtypes = [i32, i32, c_int, c_int, c_int]
     lib.dct2d_tune.argtypes = [i32, i32, c_int, c_int, i64, vp, ctypes.POINTER(ctypes.c_float)]
     lib.dct2d_copy.argtypes = [vp, vp, i64, vp]
-    lib.dct2d_image_transform.argtypes = [c_int, vp, vp, i64, i32, i32, i64, i64, vp]
+    for n in ("dct2d_image_transform", "dct2d_image_transform_noalloc"):
+        getattr(lib, n).argtypes = [c_int, vp, vp, i64, i32, i32, i64, i64, vp]
     lib.dct2d_status_string.argtypes = [c_int]
     lib.dct2d_status_string.restype = ctypes.c_char_p
     lib.dct2d_version.argtypes = []
@@ -198,16 +199,17 @@ def filter(inp, lam, out=None, stream=None):
     return out
 
 
-def image_transform(inp, out=None, direction="forward", stream=None):
+def image_transform(inp, out=None, direction="forward", stream=None, noalloc=False):
     """Batched transform of whole images of any shape with both axes in [8, 1024] (cols a multiple of
-    4), dense Q_n for axes the fast kernels do not cover (dct2d_image_transform)."""
+    4), dense Q_n for axes the fast kernels do not cover (dct2d_image_transform); noalloc=True calls
+    dct2d_image_transform_noalloc, which allocates nothing (dct2d_init must have run)."""
     import torch
     if out is None:
         out = torch.empty_like(inp)
     d = DIRECTIONS[direction] if isinstance(direction, str) else int(direction)
     batch, rows, cols, stride = _geometry(inp, None, None, None)
     _check_out(inp, out)
-    name = "dct2d_image_transform"
+    name = "dct2d_image_transform_noalloc" if noalloc else "dct2d_image_transform"
     rc = getattr(load(), name)(d, ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()), batch, rows, cols,
                                stride, stride, ctypes.c_void_p(_stream(stream)))
     _check(rc, name)

@@ -180,7 +180,10 @@ extern "C" {
 
 int dct2d_init(int device)
 {
-    const int rc = tables_init_device(device);
+    int rc = tables_init_device(device);
+    if (rc != DCT2D_OK) return rc;
+    // resolves the device address of the no-allocation entry point's scratch (no allocation)
+    rc = image_scratch_init(device);
     if (rc != DCT2D_OK) return rc;
     std::lock_guard<std::mutex> lk(g_policy_mu);
     policy_init_locked();

@@ -14,7 +14,9 @@
 // dct2d_image_transform takes its workspace from the stream-ordered allocator
 // (hipMallocAsync / hipFreeAsync on the caller's stream, so concurrent calls on different
 // streams never share it) and keeps one dense Q_n per device and length, built on first
-// use.
+// use.  dct2d_image_transform_noalloc is the same computation for callers that cannot
+// allocate: its Q tables and workspace live in `scratch`, a fixed device array of this
+// file, and the batch is processed in chunks that fit.
 #include <hip/hip_runtime.h>
 
 #include <map>
@@ -27,9 +29,22 @@ using namespace dct;
 
 namespace {
 
+// ---- the no-allocation scratch ---------------------------------------------------------
+// 64 MiB per device, held from the library's load until the process ends.  Layout per
+// call: dense Q_rows, then Q_cols (when cols != rows), then the workspace, each region
+// 256-byte aligned.  The largest shape (1024 x 1024) needs 2 x 4 MiB of tables and 4 MiB
+// per image of workspace, so every accepted shape fits at least one image per chunk.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+__device__ __align__(256) float scratch[kScratchBytes / sizeof(float)];
+
+constexpr int kMaxDevices = 64;
 std::mutex g_mu;
+// device address of `scratch` per device (the host-side name is only a stand-in)
+float* g_scratch[kMaxDevices] = {};
 // dense Q_n cache of the allocating entry point: (device, n) -> device table
 std::map<std::pair<int, int>, float*> g_q;
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 bool fast_shape(int r, int c) { return is_pow2(r) && is_pow2(c) && r >= 8 && r <= 256 && c >= 8 && c <= 256; }
 
@@ -97,7 +112,44 @@ const float* cached_q(int device, int n, int* err)
     return q;
 }
 
+// Device address of `scratch` on the current device, resolved once per device.
+float* scratch_ptr(int* err)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        *err = DCT2D_ERR_NOINIT;
+        return nullptr;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (g_scratch[dev]) return g_scratch[dev];
+    }
+    const int rc = image_scratch_init(dev);
+    if (rc != DCT2D_OK) {
+        *err = rc;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_scratch[dev];
+}
+
 } // namespace
+
+int dct::image_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return DCT2D_ERR_NOINIT;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_scratch[device]) return DCT2D_OK;
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return DCT2D_ERR_HIP;
+    if (prev != device && hipSetDevice(device) != hipSuccess) return DCT2D_ERR_HIP;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != device) hipSetDevice(prev);
+    if (e != hipSuccess || !p) return DCT2D_ERR_HIP;
+    g_scratch[device] = static_cast<float*>(p);
+    return DCT2D_OK;
+}
 
 void dct::image_release_all()
 {
@@ -141,6 +193,44 @@ int dct2d_image_transform(int dir, const float* in, float* out, int64_t batch, i
                           q_rows, q_cols, ws, s);
     }
     if (hipFreeAsync(ws, s) != hipSuccess && rc == DCT2D_OK) rc = DCT2D_ERR_HIP;
+    return rc;
+}
+
+int dct2d_image_transform_noalloc(int dir, const float* in, float* out, int64_t batch, int32_t rows, int32_t cols,
+                                  int64_t in_stride, int64_t out_stride, void* stream)
+{
+    int rc = validate(dir, in, out, batch, rows, cols, in_stride, out_stride);
+    if (rc != DCT2D_OK || batch == 0) return rc;
+    // the tables of dct2d_init; this entry point never builds them itself
+    const DeviceTables* t = tables_ready(&rc);
+    if (!t) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (fast_shape(rows, cols)) {
+        Job j{dir, in, out, batch, rows, cols, in_stride, out_stride, s, 0};
+        return dispatch(t, j, DCT2D_AUTO);
+    }
+    float* base = scratch_ptr(&rc);
+    if (!base) return rc;
+    const size_t n = (size_t)rows * cols;
+    const size_t q_rows_off = 0;
+    const size_t q_cols_off = rows == cols ? 0 : align256((size_t)rows * rows * sizeof(float));
+    const size_t ws_off = align256(q_cols_off + (size_t)cols * cols * sizeof(float));
+    if (ws_off + n * sizeof(float) > kScratchBytes) return DCT2D_ERR_SIZE; // not reached for accepted shapes
+    const int64_t fit = (int64_t)((kScratchBytes - ws_off) / (n * sizeof(float)));
+    const int64_t per = fit < 65535 ? fit : 65535;
+    char* b = reinterpret_cast<char*>(base);
+    float* q_rows = reinterpret_cast<float*>(b + q_rows_off);
+    float* q_cols = reinterpret_cast<float*>(b + q_cols_off);
+    float* ws = reinterpret_cast<float*>(b + ws_off);
+    // the tables are rebuilt on the caller's stream every call: the scratch keeps whatever
+    // the previous call on this device left in it
+    rc = tables_dense_q(rows, q_rows, s);
+    if (rc == DCT2D_OK && cols != rows) rc = tables_dense_q(cols, q_cols, s);
+    for (int64_t b0 = 0; b0 < batch && rc == DCT2D_OK; b0 += per) {
+        const int64_t c = batch - b0 < per ? batch - b0 : per;
+        rc = dense_passes(dir, in + b0 * in_stride, out + b0 * out_stride, c, rows, cols, in_stride, out_stride,
+                          q_rows, q_cols, ws, s);
+    }
     return rc;
 }
 

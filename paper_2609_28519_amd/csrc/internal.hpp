@@ -44,7 +44,9 @@ void tables_release_all();
 // with DCT2D_ERR_NOINIT; never allocates.
 const DeviceTables* tables_ready(int* err);
 
-// Whole-image transforms (image.hip): release of the dense Q cache.
+// Whole-image transforms (image.hip): per-device set-up of the no-allocation scratch
+// (resolves its device address; allocates nothing) and release of the dense Q cache.
+int image_scratch_init(int device);
 void image_release_all();
 
 // Generates dense float32 Q_n (eq. 1) for an arbitrary n into a device buffer.

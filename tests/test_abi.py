@@ -63,9 +63,9 @@ def test_argument_validation_on_host():
 
 
 def test_image_transform_validation_on_host():
-    """dct2d_image_transform validates shapes and strides before any device work."""
+    """dct2d_image_transform(_noalloc) validate shapes and strides before any device work."""
     lib = dct.load()
-    for fn in (lib.dct2d_image_transform,):
+    for fn in (lib.dct2d_image_transform, lib.dct2d_image_transform_noalloc):
         assert fn(0, None, None, 0, 600, 1000, 600000, 600000, None) == 0    # batch 0: no-op
         assert fn(0, None, None, 0, 384, 512, 384 * 512, 384 * 512, None) == 0
         assert fn(0, None, None, 0, 7, 8, 56, 56, None) == -2                # axis below 8
