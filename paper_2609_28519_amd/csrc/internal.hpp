@@ -164,6 +164,8 @@ int launch_dense_axis(const Addr& a, int64_t count, int rows, int cols, bool col
                       const float* q, hipStream_t s);
 
 int launch_fp32(const DeviceTables* t, const Job& j);
+// Rectangles with one axis of 256 and the other at most 128, fused (kern_rect256.hip).
+int launch_rect256(const DeviceTables* t, const Job& j);
 int fp32_variant_count(int rows, int cols, int dir);
 int fp32_default_variant(int rows, int cols, int dir);
 int fp32_unshared_variant(int rows, int cols, int variant);

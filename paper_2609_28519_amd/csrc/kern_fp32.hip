@@ -25,22 +25,13 @@
 // coefficients: each is multiplied by its entry of the multiplier array before the
 // inverse column transform.  The data still crosses HBM once each way.
 #include "dct1d.hpp"
+#include "fp32_common.hpp"
 #include "internal.hpp"
 
 namespace dct {
 namespace {
 
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
-
-// Returns p unchanged but opaque to the optimiser.  Used once per tile iteration so the
-// twiddle loads (scalar, cache-resident) are re-issued inside the loop instead of being
-// hoisted out of it, which would pin ~L twiddles in scalar registers for the whole
-// kernel and spill them.
-__device__ __forceinline__ twptr per_iteration(const float2* p)
-{
-    asm volatile("" : "+s"(p));
-    return (twptr)p;
-}
 
 template <int H, int W>
 struct B2D {
@@ -57,34 +48,6 @@ struct B2D {
     static constexpr int CPT = (CHUNKS + NT - 1) / NT;
     static constexpr int LDS_FLOATS = BPW * BS;
 };
-
-template <int L, int DIR>
-__device__ __forceinline__ void apply1d(float (&v)[L], twptr tw)
-{
-    if (DIR == DCT2D_FORWARD) {
-        dct2_ortho<L>(v, tw);
-    } else if (DIR == DCT2D_INVERSE) {
-        dct3_ortho<L>(v, tw);
-    } else {
-        dct2_ortho<L>(v, tw);
-        // re-read the (identical) twiddles for the inverse instead of keeping the
-        // forward's values live in scalar registers across both transforms
-        asm volatile("" : "+s"(tw));
-        dct3_ortho<L>(v, tw);
-    }
-}
-
-// Spectral filter of one column in registers: forward transform, coefficient k times
-// lam[k * pitch], inverse transform (Prop. 1, eq. 4, with the orthonormal Q).
-template <int L>
-__device__ __forceinline__ void filter1d(float (&v)[L], const gfloat* lam, int pitch, twptr tw)
-{
-    dct2_ortho<L>(v, tw);
-#pragma unroll
-    for (int k = 0; k < L; ++k) v[k] *= lam[k * pitch];
-    asm volatile("" : "+s"(tw));
-    dct3_ortho<L>(v, tw);
-}
 
 // Filter step of the split kernels: o[k] *= lam[k * PITCH + off] for k < N, lam wave-uniform.
 // Every o[k] is final before the first multiplier load (the loads' offsets depend on a value
@@ -1710,7 +1673,11 @@ int launch_fused(const DeviceTables* t, const Job& j)
 //   256 x 256:        0 split fused (two groups of wavefronts, two LDS rounds), one
 //                     resident workgroup per CU; 1 two-pass; 2 split fused, one array
 //                     per workgroup; 3, 4 as 0 with the two cohorts of CUs staggered
-//   other, an axis of 256: 0 two-pass
+//   one axis of 256, the other <= 128: 0 fused (k_rect256: the tile in LDS, the length-256
+//                     transforms shared by four wavefront roles), one tile per workgroup;
+//                     1 two-pass; 2 as 0 with resident workgroups looping over the tiles;
+//                     3 (short axis <= 64) k_rect256_db: one persistent workgroup per CU, two
+//                     tile buffers filled by LDS DMA while the other is transformed
 int fp32_variant_count(int rows, int cols, int)
 {
     if (rows == 64 && cols == 64) return 16;
@@ -1718,7 +1685,7 @@ int fp32_variant_count(int rows, int cols, int)
     if (rows == 128 && cols == 128) return 6;
     if (rows <= 128 && cols <= 128) return 2;
     if (rows == 256 && cols == 256) return 5;
-    return 1;
+    return (rows == 256 ? cols : rows) <= 64 ? 4 : 3; // variant 3: short axis <= 64 only
 }
 
 // Variant used until the tuner measures otherwise (fastest in measurements on MI355X
@@ -1739,6 +1706,14 @@ int fp32_default_variant(int rows, int cols, int dir)
     }
     if (rows == 128 && cols == 128) return 4;
     if (rows == 256 && cols == 256) return 4;
+    if ((rows == 256) != (cols == 256)) {
+        // measured on 512 MiB batches: the double-buffered kernel wherever it leads
+        const bool wide = cols == 256;
+        const int s = wide ? rows : cols;
+        if (s == 128) return dir == DCT2D_FORWARD ? 1 : wide ? 0 : 2;
+        if (dir != DCT2D_ROUNDTRIP) return 3;
+        return wide || s >= 32 ? 0 : 3; // the round trip's arithmetic wants two workgroups per CU
+    }
     return 0;
 }
 
@@ -1753,6 +1728,7 @@ int fp32_unshared_variant(int rows, int cols, int v)
     if (rows <= 64 && cols <= 64) return v == 0 ? 3 : v;
     if (rows == 128 && cols == 128) return v == 0 ? 5 : v == 3 ? 4 : v;
     if (rows == 256 && cols == 256) return v == 0 || v == 3 || v == 4 ? 2 : v;
+    if ((rows == 256) != (cols == 256)) return v == 2 || v == 3 ? 0 : v;
     return v;
 }
 
@@ -1771,6 +1747,7 @@ int launch_fp32(const DeviceTables* t, const Job& j)
     }
     if (j.rows <= 128 && j.cols <= 128 && j.variant == 0) return launch_fused(t, j);
     if (j.rows == 256 && j.cols == 256 && j.variant != 1) return launch_split256(t, j);
+    if ((j.rows == 256) != (j.cols == 256) && j.variant != 1) return launch_rect256(t, j);
     return launch_two_pass(t, j);
 }
 

@@ -207,9 +207,11 @@ __device__ __forceinline__ f32x4 pass16(const float (&d)[4], const B16<N, MODE>&
 #pragma unroll
             for (int i = 0; i < ModeInfo<MODE>::parts; ++i) x[i][j] = p[i];
         }
-        // Chained products stay on one instruction shape: a K=32 accumulate feeding a
-        // K=16 one gave wrong sums, so two-part modes pair (X1 C0 + X0 C1) and then
-        // (X0 C0 + 0) on K=32 instructions.
+        // Two split products share one K=32 instruction (k slots 0-3 carry one product's
+        // four k values, slots 4-7 the other's, over the same four k values of the
+        // lane), so two-part modes issue (X1 C0 + X0 C1) and then (X0 C0 + 0), smallest
+        // terms first.  The 16x16x16 and 16x16x32 shapes share the accumulator layout,
+        // so a chain may mix them; keeping one shape only makes the issue pattern uniform.
         constexpr float z4[4] = {0.f, 0.f, 0.f, 0.f};
         if constexpr (ModeInfo<MODE>::f16 && ModeInfo<MODE>::parts == 2) {
             acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(make8<f16x8, _Float16>(x[1], x[0]),

@@ -117,7 +117,8 @@ def test_zero_multipliers_and_zero_blocks(h, w):
     assert np.all(y[1] == 0.0)
 
 
-@pytest.mark.parametrize("h,w", ((8, 8), (32, 32), (64, 64), (128, 128), (256, 256), (8, 64)))
+@pytest.mark.parametrize("h,w", ((8, 8), (32, 32), (64, 64), (128, 128), (256, 256), (8, 64), (8, 256), (256, 32),
+                                 (128, 256)))
 def test_filter_every_variant(h, w):
     """Every kernel variant the autotuner may freeze for the filter carries the multiply."""
     dct = _lib()
@@ -132,6 +133,37 @@ def test_filter_every_variant(h, w):
             y, _ = _filter(x, lam)
             e = _score(x, y, lam)
             assert np.isfinite(e).all() and e.max() <= GATE, "%dx%d v%d: %.3e" % (h, w, v, e.max())
+    finally:
+        dct.set_variant(h, w, "filter", "fp32", keep)
+
+
+@pytest.mark.parametrize("h,w", ((8, 256), (256, 32), (64, 256)))
+def test_filter_rect256_every_variant_many_tiles(h, w):
+    """Rectangles with a 256 axis, every variant, per-array multipliers, about three tiles per CU
+    plus a ragged last tile (the persistent schedules run every stage of their loops); arrays
+    spread over the batch are scored against the oracle."""
+    import torch
+    from tests.gpu_util import spread
+    dct = _lib()
+    s = w if h == 256 else h
+    per_tile = max(1, 64 // s)
+    batch = per_tile * (3 * 256 + 5) - (per_tile - 1)
+    g = np.random.default_rng(5 * h + w)
+    x = g.standard_normal((batch, h, w)).astype(np.float32)
+    lam = g.uniform(-2.0, 2.0, (batch, h, w)).astype(np.float32)
+    idx = spread(batch, 100, seed=h * w)
+    sel = torch.from_numpy(idx).cuda()
+    x_dev, lam_dev = to_gpu(x), to_gpu(lam)
+    keep = dct.get_variant(h, w, "filter", "fp32")
+    try:
+        for v in range(dct.variant_count(h, w, "filter", "fp32")):
+            dct.set_variant(h, w, "filter", "fp32", v)
+            out = dct.filter(x_dev, lam_dev)
+            torch.cuda.synchronize()
+            e = _score(x[idx], out[sel].cpu().numpy(), lam[idx])
+            assert np.isfinite(e).all() and e.max() <= GATE, "%dx%d v%d: %.3e at array %d" % (
+                h, w, v, e.max(), idx[int(np.argmax(e))])
+            del out
     finally:
         dct.set_variant(h, w, "filter", "fp32", keep)
 

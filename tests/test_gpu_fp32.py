@@ -52,8 +52,9 @@ def test_square_sizes_ragged_tail(n, direction):
     assert_parity(x, y, direction, label="N=%d" % n)
 
 
-@pytest.mark.parametrize("h,w", [(8, 16), (16, 8), (8, 64), (64, 8), (32, 128), (128, 32), (16, 256),
-                                 (256, 8), (64, 256), (256, 128), (128, 64)])
+@pytest.mark.parametrize("h,w", [(8, 16), (16, 8), (8, 64), (64, 8), (32, 128), (128, 32), (128, 64),
+                                 (8, 256), (256, 8), (16, 256), (256, 16), (32, 256), (256, 32), (64, 256),
+                                 (256, 64), (128, 256), (256, 128)])
 @pytest.mark.parametrize("direction", DIRS)
 def test_rectangles(h, w, direction):
     """Rectangular arrays Q_h X Q_w^T (Section 7.1)."""
@@ -240,8 +241,39 @@ def test_full_batch_every_looping_variant(n, variants):
             dct.set_variant(n, n, d, "fp32", keep[d])
 
 
+@pytest.mark.parametrize("h,w", [(8, 256), (256, 8), (16, 256), (256, 32), (64, 256), (256, 64), (128, 256)])
+def test_rect256_every_variant_many_tiles(h, w):
+    """Rectangles with a 256 axis in every variant, at a batch of about three tiles per CU plus a
+    ragged last tile (a tile is 64 long lines: 64 / short-axis arrays, or one array for a short
+    axis of 64 or 128), so that the persistent schedules (one or two resident workgroups per CU,
+    one of them double-buffered) run every stage of their loops, in place, every direction:
+    sampled arrays against the oracle, every array against its closed form."""
+    from tests.gpu_util import spread
+    dct = _lib()
+    s = w if h == 256 else h
+    per_tile = max(1, 64 // s) if s <= 64 else 1
+    batch = per_tile * (3 * 256 + 5) - (per_tile - 1 if per_tile > 1 else 0)
+    g = np.random.default_rng(h * 7 + w)
+    x = g.standard_normal((batch, h, w)).astype(np.float32)
+    idx = spread(batch, 120, seed=h + w)
+    xs = x[idx].copy()
+    refs = _sample_refs(xs)
+    x_dev = to_gpu(x)
+    del x
+    keep = {d: dct.get_variant(h, w, d, "fp32") for d in DIRS}
+    try:
+        for v in range(dct.variant_count(h, w, "forward", "fp32")):
+            for d in DIRS:
+                dct.set_variant(h, w, d, "fp32", v)
+            _full_batch_check(dct, s, x_dev, xs, idx, refs, "%dx%d v%d" % (h, w, v),
+                              lambda d, t: dct.transform(t, t, d, "fp32"))
+    finally:
+        for d in DIRS:
+            dct.set_variant(h, w, d, "fp32", keep[d])
+
+
 @pytest.mark.parametrize("h,w", [(8, 8), (16, 16), (32, 32), (64, 64), (128, 128), (256, 256), (8, 64), (64, 16),
-                                 (128, 32), (256, 64)])
+                                 (128, 32), (256, 64), (8, 256), (128, 256), (256, 16)])
 @pytest.mark.parametrize("direction", DIRS)
 def test_every_variant(h, w, direction):
     """Every kernel variant the autotuner may pick meets the gate (the policy only changes speed)."""
