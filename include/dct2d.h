@@ -31,11 +31,16 @@
  * launch errors; a fault during execution surfaces at the caller's synchronisation.
  *
  * Sizes accepted by the three basic calls and dct2d_transform_ex: rows and cols each
- * a power of two in [8, 256] (squares and rectangles).  Any other length returns
- * DCT2D_ERR_SIZE: like the paper (Section 7.1) the basic API rejects
- * non-power-of-two axes instead of zero-padding, which would change the transform.
- * Ragged plans additionally accept whole images with axes up to 1024, including
- * non-power-of-two lengths (computed exactly from the dense Q_n of eq. 1).
+ * a power of two in [8, 1024] (squares and rectangles).  Axes up to 256 run the fused
+ * kernels; a shape with an axis of 512 or 1024 runs the dense image passes of
+ * dct2d_image_transform (one float32 product per axis against Q_n, a workspace of one
+ * image per image taken from the stream-ordered allocator on `stream`), on the float32
+ * path only (any other precision: DCT2D_ERR_PRECISION).  The variant, autotuner and
+ * filter calls cover axes up to 256.  Any other length returns DCT2D_ERR_SIZE: like the
+ * paper (Section 7.1) the basic API rejects non-power-of-two axes instead of
+ * zero-padding, which would change the transform.  dct2d_image_transform and ragged
+ * plans accept whole images with any axes in [8, 1024], including non-power-of-two
+ * lengths (computed exactly from the dense Q_n of eq. 1).
  *
  * Alignment: `data`/`in`/`out` must be 16-byte aligned and strides multiples of 4
  * floats (DCT2D_ERR_ALIGN otherwise).

@@ -52,6 +52,15 @@ bool basic_size_ok(int rows, int cols)
     return is_pow2(rows) && is_pow2(cols) && rows >= 8 && rows <= 256 && cols >= 8 && cols <= 256;
 }
 
+// Power-of-two shapes with an axis of 512 or 1024 (the other 8 .. 1024): accepted by the
+// transform calls and computed by the dense image passes (one product per axis against the
+// FP64-built Q_n, float32); no kernel variants, float32 path only.
+bool long_axis_size_ok(int rows, int cols)
+{
+    return is_pow2(rows) && is_pow2(cols) && rows >= 8 && rows <= 1024 && cols >= 8 && cols <= 1024 &&
+           (rows > 256 || cols > 256);
+}
+
 int variant_for(int rows, int cols, int dir, int prec)
 {
     std::lock_guard<std::mutex> lk(g_policy_mu);
@@ -86,7 +95,7 @@ int validate(int dir, const float* in, const float* out, int64_t batch, int32_t 
     if (dir < DCT2D_FORWARD || dir > DCT2D_ROUNDTRIP) return DCT2D_ERR_ARG;
     if (prec < 0 || prec >= kNumPrec) return DCT2D_ERR_ARG;
     if (batch < 0) return DCT2D_ERR_ARG;
-    if (!basic_size_ok(rows, cols)) return DCT2D_ERR_SIZE;
+    if (!basic_size_ok(rows, cols) && !long_axis_size_ok(rows, cols)) return DCT2D_ERR_SIZE;
     const int64_t n = (int64_t)rows * cols;
     if (in_stride < n || out_stride < n) return DCT2D_ERR_STRIDE;
     if (batch == 0) return DCT2D_OK;
@@ -111,7 +120,12 @@ int run(int dir, const float* in, float* out, int64_t batch, int32_t rows, int32
         int64_t out_stride, int prec, void* stream)
 {
     int rc = validate(dir, in, out, batch, rows, cols, in_stride, out_stride, prec);
-    if (rc != DCT2D_OK || batch == 0) return rc;
+    if (rc != DCT2D_OK) return rc;
+    if (long_axis_size_ok(rows, cols)) {
+        if (prec != DCT2D_FP32 && prec != DCT2D_AUTO) return DCT2D_ERR_PRECISION;
+        return dct2d_image_transform(dir, in, out, batch, rows, cols, in_stride, out_stride, stream);
+    }
+    if (batch == 0) return rc;
     const DeviceTables* t = tables_current(&rc);
     if (!t) return rc;
     Job j{dir, in, out, batch, rows, cols, in_stride, out_stride, static_cast<hipStream_t>(stream), 0};
@@ -220,6 +234,7 @@ int dct2d_transform_ex(int dir, const float* in, float* out, int64_t batch, int3
 int dct2d_filter(const float* in, float* out, int64_t batch, int32_t rows, int32_t cols, int64_t in_stride,
                  int64_t out_stride, const float* lambda, int64_t lambda_stride, void* stream)
 {
+    if (!basic_size_ok(rows, cols)) return DCT2D_ERR_SIZE; // the fused kernels cover axes <= 256
     int rc = validate(DCT2D_ROUNDTRIP, in, out, batch, rows, cols, in_stride, out_stride, DCT2D_FP32);
     if (rc != DCT2D_OK) return rc;
     const int64_t n = (int64_t)rows * cols;

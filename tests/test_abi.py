@@ -34,8 +34,9 @@ def test_status_strings_and_version():
     assert "gfx950" in dct.version()
 
 
-@pytest.mark.parametrize("rows,cols,code", [(26, 32, -2), (32, 26, -2), (384, 384, -2), (512, 512, -2),
-                                            (4, 4, -2), (0, 8, -2), (8, 8, 0)])
+@pytest.mark.parametrize("rows,cols,code", [(26, 32, -2), (32, 26, -2), (384, 384, -2), (512, 512, 0),
+                                            (1024, 8, 0), (8, 1024, 0), (1024, 1024, 0), (2048, 8, -2),
+                                            (8, 2048, -2), (4, 4, -2), (0, 8, -2), (8, 8, 0)])
 def test_size_validation_on_host(rows, cols, code):
     lib = dct.load()
     # batch = 0 never touches the device: only validation runs
@@ -58,6 +59,12 @@ def test_argument_validation_on_host():
     assert lib.dct2d_transform_ex(0, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1100), 4, 8, 8, 64, 64, 0,
                                   None) == -1
     assert lib.dct2d_variant_count(26, 8, 0, 0) == 0
+    # axes of 512 and 1024: float32 path only; no variants, tuner or filter
+    assert lib.dct2d_transform_ex(0, None, None, 0, 512, 512, 512 * 512, 512 * 512, 4, None) == -5
+    assert lib.dct2d_transform_ex(1, None, None, 0, 1024, 64, 1024 * 64, 1024 * 64, 7, None) == 0
+    assert lib.dct2d_variant_count(512, 512, 0, 0) == 0
+    assert lib.dct2d_get_variant(1024, 8, 0, 0) == -2
+    assert lib.dct2d_filter(None, None, 0, 512, 512, 512 * 512, 512 * 512, None, 0, None) == -2
     assert lib.dct2d_get_variant(26, 8, 0, 0) == -2
     assert lib.dct2d_set_variant(8, 8, 0, 0, 99) == -1
 

@@ -65,6 +65,31 @@ def test_rectangles(h, w, direction):
     assert_parity(x, y, direction, label="%dx%d" % (h, w))
 
 
+@pytest.mark.parametrize("h,w", [(512, 512), (1024, 1024), (8, 1024), (1024, 16), (256, 512), (512, 64)])
+@pytest.mark.parametrize("direction", DIRS)
+def test_long_axes_basic_calls(h, w, direction):
+    """Axes of 512 and 1024 through the in-place basic calls (dense image passes behind them):
+    several arrays, every one checked against the oracle."""
+    import torch
+    dct = _lib()
+    g = np.random.default_rng(h + 7 * w)
+    batch = max(2, min(9, (1 << 22) // (h * w)))
+    x = g.standard_normal((batch, h, w)).astype(np.float32)
+    t = to_gpu(x)
+    {"forward": dct.forward_, "inverse": dct.inverse_, "roundtrip": dct.roundtrip_}[direction](t)
+    torch.cuda.synchronize()
+    assert_parity(x, t.cpu().numpy(), direction, label="%dx%d" % (h, w))
+
+
+def test_long_axes_other_precisions_rejected():
+    """Only the float32 path exists for axes of 512 and 1024."""
+    dct = _lib()
+    x = to_gpu(np.zeros((2, 512, 512), np.float32))
+    with pytest.raises(dct.DCT2DError) as e:
+        dct.transform(x, None, "forward", "bf16")
+    assert e.value.code == -5  # DCT2D_ERR_PRECISION
+
+
 @pytest.mark.parametrize("n", (8, 64, 256))
 def test_inverse_of_stored_spectrum(n):
     """Inverse applied to fl32(C(X)) recovers X (the inverse's own input is the spectrum)."""
