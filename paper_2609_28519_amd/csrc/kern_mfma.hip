@@ -268,8 +268,11 @@ k_mfma16(Addr a, int64_t batch, QTab q)
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
     const int64_t ntiles = (batch + BPT - 1) / BPT;
 
-    // which block of the tile this lane's loaded values belong to, and the offset
-    // of its 16 bytes inside that block
+    // The tile (1 KB: one 16 x 16 block, or four 8 x 8 blocks) moves between HBM and the
+    // registers as 64 lane-consecutive 16-byte chunks (lane l loads and stores chunk l, so
+    // every group of four lanes covers one 64-byte segment); a lane permutation
+    // (ds_bpermute) maps the chunks to and from the operand layout, in which lane (g, c) holds
+    // chunk `need`: block blk, 16 bytes at float offset off of the block.
     int blk, off;
     if (N == 8) {
         blk = (c >> 3) * 2 + (g >> 1);
@@ -278,6 +281,16 @@ k_mfma16(Addr a, int64_t batch, QTab q)
         blk = 0;
         off = c * 16 + 4 * g;
     }
+    const int need = (blk * N * N + off) / 4;
+    // the lane whose operand-layout values form chunk `lane` (inverse of need)
+    int holder;
+    if (N == 8) {
+        const int b8 = lane >> 4, rem = lane & 15;
+        holder = 16 * ((b8 & 1) * 2 + (rem & 1)) + (b8 >> 1) * 8 + (rem >> 1);
+    } else {
+        holder = 16 * (lane & 3) + (lane >> 2);
+    }
+    const int my_blk = N == 8 ? lane >> 4 : 0; // block of the chunk this lane moves
     // the forward multiplies by Q^T, the inverse by Q; the round trip needs both
     const B16<N, MODE> bf = load_b16<N, MODE>(q, false, g, c);
     const B16<N, MODE> bi = load_b16<N, MODE>(q, true, g, c);
@@ -293,11 +306,14 @@ k_mfma16(Addr a, int64_t batch, QTab q)
         bool valid[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            const int64_t b = (t0 + u) * BPT + blk;
+            const int64_t b = (t0 + u) * BPT + my_blk;
             valid[u] = (t0 + u) < ntiles && b < batch;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (valid[u]) v = *reinterpret_cast<const gfloat4*>(a.src(b) + off);
-            d[u][0] = v.x; d[u][1] = v.y; d[u][2] = v.z; d[u][3] = v.w;
+            if (valid[u]) v = *reinterpret_cast<const gfloat4*>(a.src(b) + 4 * (lane & (N == 8 ? 15 : 63)));
+            d[u][0] = __shfl(v.x, need, 64);
+            d[u][1] = __shfl(v.y, need, 64);
+            d[u][2] = __shfl(v.z, need, 64);
+            d[u][3] = __shfl(v.w, need, 64);
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
@@ -337,11 +353,13 @@ k_mfma16(Addr a, int64_t batch, QTab q)
                     for (int j = 0; j < 4; ++j) d[u][j] = ldexpf(d[u][j], -e1);
                 }
             }
+            const float4 o = make_float4(__shfl(ldexpf(d[u][0], etot), holder, 64),
+                                         __shfl(ldexpf(d[u][1], etot), holder, 64),
+                                         __shfl(ldexpf(d[u][2], etot), holder, 64),
+                                         __shfl(ldexpf(d[u][3], etot), holder, 64));
             if (valid[u]) {
-                const int64_t b = (t0 + u) * BPT + blk;
-                *reinterpret_cast<gfloat4*>(a.dst(b) + off) =
-                    make_float4(ldexpf(d[u][0], etot), ldexpf(d[u][1], etot), ldexpf(d[u][2], etot),
-                                ldexpf(d[u][3], etot));
+                const int64_t b = (t0 + u) * BPT + my_blk;
+                *reinterpret_cast<gfloat4*>(a.dst(b) + 4 * (lane & (N == 8 ? 15 : 63))) = o;
             }
         }
     }
@@ -624,50 +642,62 @@ k_mfma32(Addr a, int64_t batch, QTab q)
 // tile (I, J) of a pass is sum_K A(I, K) B(K, J), eight tile products per pass.  The
 // accumulator of tile (K, I) after pass 1 serves as the A operand of tile (I, K) in pass 2
 // (the same transpose-by-reuse as the 32 x 32 kernel, applied tile-wise).
-// B tile (K, J) of Q^T (forward) or Q (inverse), split part p, in the lane's slots:
-// bt[p][s][j] = B[32 K + k(s, j)][32 J + c].  Read from the (cache-resident) tables at use:
-// B[k][n] is entry (n, k) of Q (forward) or of Q^T (inverse), so a lane's slots are runs
-// of four consecutive entries in either direction.
+//
+// B operands live in LDS, built once per workgroup: operand (K, J, part p, instruction half s)
+// of a direction holds, for lane (h, c), the eight 16-bit (fp8: 8-bit) values
+// B[32 K + k(s, j)][32 J + c], k(s, j) = 8 (2 s + j / 4) + 4 h + j % 4, where B[k][n] is entry
+// (n, k) of Q (forward) or of Q^T (inverse); a lane reads one operand with one 16-byte (fp8:
+// 8-byte) access, consecutive lanes on consecutive addresses.  24 operands per direction
+// (24 KB; the round trip keeps both directions).  The A tile is split into packed parts once
+// per (I, K) and stays in registers as 16-bit vectors.
+constexpr int kB64Ops = 24; // (K, J, p, s)
+
+__host__ __device__ constexpr int b64_op(int K, int J, int p, int s) { return ((K * 2 + J) * 3 + p) * 2 + s; }
+
+// Builds the B operands of `ndir` directions (d = 0: the first pass's, d = 1: the inverse's
+// for the round trip) in LDS; every thread of the workgroup takes part.
 template <int MODE>
-__device__ __forceinline__ void load_b64_tile(float (&bt)[3][2][8], const QTab& q, bool inv, int h, int c, int K,
-                                              int J)
+__device__ __forceinline__ void fill_b64(uint4* lds, const QTab& q, int ndir, bool first_inv)
 {
-#pragma unroll
-    for (int p = 0; p < 3; ++p)
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
+    constexpr bool F8 = ModeInfo<MODE>::f8;
+    const int nent = ndir * kB64Ops * 64; // (direction, operand, lane)
+    for (int e = threadIdx.x; e < nent; e += blockDim.x) {
+        const int lane = e & 63, op = (e >> 6) % kB64Ops, d = e / (64 * kB64Ops);
+        const bool inv = d == 0 ? first_inv : true;
+        const int s = op & 1, p = (op >> 1) % 3, J = (op / 6) & 1, K = op / 12;
+        const int h = lane >> 5, c = lane & 31;
+        const int n = 32 * J + c;
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+        if (F8 ? p == 0 : p < ModeInfo<MODE>::parts) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int k = 32 * K + 8 * (2 * s + j / 4) + 4 * h + (j & 3);
-                const int n = 32 * J + c;
-                float v = 0.f;
-                if (p < ModeInfo<MODE>::parts) {
-                    const int i = n * 64 + k;
-                    v = ModeInfo<MODE>::f16 ? f16_bits_to_f((inv ? q.hft : q.hf)[p * 4096 + i])
-                                            : bf16_bits_to_f((inv ? q.bft : q.bf)[p * 4096 + i]);
+                const int i = n * 64 + k;
+                if constexpr (F8) {
+                    const uint32_t byte = (inv ? q.f8t : q.f8)[i];
+                    w[j / 4] |= byte << (8 * (j & 3));
+                } else {
+                    const uint32_t bits = ModeInfo<MODE>::f16 ? (inv ? q.hft : q.hf)[p * 4096 + i]
+                                                              : (inv ? q.bft : q.bf)[p * 4096 + i];
+                    w[j / 2] |= bits << (16 * (j & 1));
                 }
-                bt[p][s][j] = v;
             }
-}
-
-template <int MODE>
-__device__ __forceinline__ long load_b64_f8(const QTab& q, bool inv, int h, int c, int K, int J, int s)
-{
-    uint64_t v = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int k = 32 * K + 8 * (2 * s + j / 4) + 4 * h + (j & 3);
-        const int n = 32 * J + c;
-        const uint8_t byte = (inv ? q.f8t : q.f8)[n * 64 + k];
-        v |= (uint64_t)byte << (8 * j);
+        }
+        lds[e] = make_uint4(w[0], w[1], w[2], w[3]);
     }
-    return (long)v;
 }
 
-// acc(I, J) += A(I, K) * B(K, J) over the kept split products; a = the lane's 16 values of
-// the A tile, already split into parts x[part][16].
-template <int MODE>
-__device__ __forceinline__ void tile_products(f32x16& acc, const float (&x)[3][16], const float (&bq)[3][2][8])
+template <class V>
+__device__ __forceinline__ V lds_b8(const uint4* lds, int d, int op, int lane)
+{
+    return __builtin_bit_cast(V, lds[(d * kB64Ops + op) * 64 + lane]);
+}
+
+// acc(I, J) += A(I, K) * B(K, J) over the kept split products (smallest terms first);
+// av[i][s]: part i of the A tile's k-slots of instruction half s.
+template <int MODE, class V>
+__device__ __forceinline__ void tile_products(f32x16& acc, const V (&av)[3][2], const uint4* lds, int d, int K, int J,
+                                              int lane)
 {
     constexpr int P = ModeInfo<MODE>::parts;
 #pragma unroll
@@ -677,26 +707,33 @@ __device__ __forceinline__ void tile_products(f32x16& acc, const float (&x)[3][1
             const int p = sum - i;
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
+                const V bv = lds_b8<V>(lds, d, b64_op(K, J, p, s), lane);
                 if constexpr (ModeInfo<MODE>::f16)
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(vec8<f16x8, _Float16>(&x[i][8 * s]),
-                                                                 vec8<f16x8, _Float16>(bq[p][s]), acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(av[i][s], bv, acc, 0, 0, 0);
                 else
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vec8<bf16x8, __bf16>(&x[i][8 * s]),
-                                                                  vec8<bf16x8, __bf16>(bq[p][s]), acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[i][s], bv, acc, 0, 0, 0);
             }
         }
 }
 
+// Two workgroups per CU (at most 256 registers per lane, the accumulators included) where
+// the kernel fits them without spilling; the three-part round trip keeps one.
 template <int MODE, int DIR>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, (MODE == M_BF16X6 && DIR == DCT2D_ROUNDTRIP) ? 1 : 2)
 k_mfma64(Addr a, int64_t batch, QTab q)
 {
     constexpr int T0 = ModeInfo<MODE>::target;
+    constexpr int NDIR = DIR == DCT2D_ROUNDTRIP ? 2 : 1;
+    __shared__ uint4 bl[NDIR * kB64Ops * 64];
+    fill_b64<MODE>(bl, q, NDIR, DIR == DCT2D_INVERSE);
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int h = lane >> 5, c = lane & 31;
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
     const float qscale = MODE == M_FP8 ? 1.0f / (float)(1 << kF8QShift) : 1.0f;
+    using V = typename std::conditional<ModeInfo<MODE>::f16, f16x8, bf16x8>::type;
+    using E = typename std::conditional<ModeInfo<MODE>::f16, _Float16, __bf16>::type;
     for (int64_t b = wave; b < batch; b += nwaves) {
         // d[I][K][16]: lane (h, c) holds row 32 I + c, columns 32 K + 8 qq + 4 h .. +3
         float d[2][2][16];
@@ -730,7 +767,7 @@ k_mfma64(Addr a, int64_t batch, QTab q)
         constexpr int npass = DIR == DCT2D_ROUNDTRIP ? 4 : 2;
 #pragma unroll
         for (int ps = 0; ps < npass; ++ps) {
-            const bool inv = DIR == DCT2D_INVERSE || (DIR == DCT2D_ROUNDTRIP && ps >= 2);
+            const int dsel = DIR == DCT2D_ROUNDTRIP && ps >= 2 ? 1 : 0;
             f32x16 acc[2][2];
 #pragma unroll
             for (int I = 0; I < 2; ++I)
@@ -755,24 +792,23 @@ k_mfma64(Addr a, int64_t batch, QTab q)
                                 int hi = __builtin_amdgcn_cvt_pk_fp8_f32(at[8 * s + 4], at[8 * s + 5], 0, false);
                                 hi = __builtin_amdgcn_cvt_pk_fp8_f32(at[8 * s + 6], at[8 * s + 7], hi, true);
                                 const long av = (long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-                                acc[I][J] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(
-                                    av, load_b64_f8<MODE>(q, inv, h, c, K, J, s), acc[I][J], 0, 0, 0);
+                                const uint4 bw = bl[(dsel * kB64Ops + b64_op(K, J, 0, s)) * 64 + lane];
+                                const long bv = (long)(((uint64_t)bw.y << 32) | bw.x);
+                                acc[I][J] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(av, bv, acc[I][J], 0, 0, 0);
                             }
                     } else {
-                        float x[3][16];
+                        V av[3][2];
 #pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            float pp[3];
-                            split<MODE>(at[r], pp);
+                        for (int s = 0; s < 2; ++s)
 #pragma unroll
-                            for (int i = 0; i < ModeInfo<MODE>::parts; ++i) x[i][r] = pp[i];
-                        }
+                            for (int r = 0; r < 8; ++r) {
+                                float pp[3];
+                                split<MODE>(at[8 * s + r], pp);
 #pragma unroll
-                        for (int J = 0; J < 2; ++J) {
-                            float bt[3][2][8];
-                            load_b64_tile<MODE>(bt, q, inv, h, c, K, J);
-                            tile_products<MODE>(acc[I][J], x, bt);
-                        }
+                                for (int i = 0; i < ModeInfo<MODE>::parts; ++i) av[i][s][r] = (E)pp[i];
+                            }
+#pragma unroll
+                        for (int J = 0; J < 2; ++J) tile_products<MODE, V>(acc[I][J], av, bl, dsel, K, J, lane);
                     }
                 }
 #pragma unroll
@@ -823,14 +859,22 @@ QTab qtab(const DeviceTables* t, int n)
     return QTab{t->q_bf16[i], t->q_f16[i], t->q_f8[i], n, t->q_bf16_t[i], t->q_f16_t[i], t->q_f8_t[i]};
 }
 
+// Resident wavefronts per CU of the grid-stride variants: all 32 the kernels' registers allow,
+// or fewer (variants 4 and up) when fewer bytes in flight per CU keep HBM closer to its
+// streaming rate.
+int waves_per_cu(int variant)
+{
+    return variant == 4 || variant == 6 ? 16 : variant == 5 || variant == 7 ? 8 : 32;
+}
+
 template <int N, int MODE, int DIR, int UNROLL>
 int go16(const DeviceTables* t, const Job& j)
 {
     constexpr int BPT = N == 8 ? 4 : 1;
     const int64_t ntiles = (j.batch + BPT - 1) / BPT;
     const int64_t waves_needed = (ntiles + UNROLL - 1) / UNROLL;
-    // variant 3: one iteration per wavefront (no grid-stride reuse); otherwise 8 waves per SIMD
-    const int64_t cap = j.variant == 3 ? ((int64_t)1 << 32) : (int64_t)t->num_cu * 32;
+    // variant 3: one iteration per wavefront (no grid-stride reuse); otherwise grid-stride
+    const int64_t cap = j.variant == 3 ? ((int64_t)1 << 32) : (int64_t)t->num_cu * waves_per_cu(j.variant);
     const int64_t waves = waves_needed < cap ? waves_needed : cap;
     const unsigned grid = (unsigned)((waves + 3) / 4);
     k_mfma16<N, MODE, DIR, UNROLL><<<grid, 256, 0, j.stream>>>(j.addr(), j.batch, qtab(t, N));
@@ -841,7 +885,7 @@ template <int MODE, int DIR, int UNROLL>
 int go32(const DeviceTables* t, const Job& j)
 {
     const int64_t waves_needed = (j.batch + UNROLL - 1) / UNROLL;
-    const int64_t cap = (int64_t)t->num_cu * 32;
+    const int64_t cap = (int64_t)t->num_cu * waves_per_cu(j.variant);
     const int64_t waves = waves_needed < cap ? waves_needed : cap;
     const unsigned grid = (unsigned)((waves + 3) / 4);
     k_mfma32<MODE, DIR, UNROLL><<<grid, 256, 0, j.stream>>>(j.addr(), j.batch, qtab(t, 32));
@@ -851,7 +895,16 @@ int go32(const DeviceTables* t, const Job& j)
 template <int MODE, int DIR>
 int go64(const DeviceTables* t, const Job& j)
 {
-    const int64_t cap = (int64_t)t->num_cu * 16;
+    // grid-stride over blocks with only resident workgroups (registers and the LDS operand
+    // table bound the residency): a workgroup that waits for a slot would run its share of
+    // the blocks after the others have finished
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mfma64<MODE, DIR>, 256, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    // variants 1 and 2: at most two / one workgroup per CU (fewer blocks in flight per CU)
+    if (j.variant == 1 && per_cu > 2) per_cu = 2;
+    if (j.variant == 2) per_cu = 1;
+    const int64_t cap = (int64_t)t->num_cu * per_cu * 4;
     const int64_t waves = j.batch < cap ? j.batch : cap;
     const unsigned grid = (unsigned)((waves + 3) / 4);
     k_mfma64<MODE, DIR><<<grid, 256, 0, j.stream>>>(j.addr(), j.batch, qtab(t, 64));
@@ -861,19 +914,18 @@ int go64(const DeviceTables* t, const Job& j)
 template <int MODE, int DIR>
 int go_unroll(const DeviceTables* t, const Job& j)
 {
-    // variant = unroll choice: 0 -> 2 tiles per iteration, 1 -> 1, 2 -> 4
+    // variant = unroll choice: 0 -> 2 tiles per iteration, 1 -> 1, 2 -> 4; 3: unroll 1, one
+    // iteration per wavefront (16 x 16 tiles only); 4, 5: unroll 1 with 16 / 8 wavefronts per
+    // CU; 6, 7: unroll 2 with 16 / 8 wavefronts per CU
+    const int v = j.variant;
+    const bool u1 = v == 1 || v == 3 || v == 4 || v == 5, u4 = v == 2;
     switch (j.rows) {
     case 8:
-        return j.variant == 1 || j.variant == 3 ? go16<8, MODE, DIR, 1>(t, j)
-               : j.variant == 2                 ? go16<8, MODE, DIR, 4>(t, j)
-                                                : go16<8, MODE, DIR, 2>(t, j);
+        return u1 ? go16<8, MODE, DIR, 1>(t, j) : u4 ? go16<8, MODE, DIR, 4>(t, j) : go16<8, MODE, DIR, 2>(t, j);
     case 16:
-        return j.variant == 1 || j.variant == 3 ? go16<16, MODE, DIR, 1>(t, j)
-               : j.variant == 2                 ? go16<16, MODE, DIR, 4>(t, j)
-                                                : go16<16, MODE, DIR, 2>(t, j);
+        return u1 ? go16<16, MODE, DIR, 1>(t, j) : u4 ? go16<16, MODE, DIR, 4>(t, j) : go16<16, MODE, DIR, 2>(t, j);
     case 32:
-        return j.variant == 1 ? go32<MODE, DIR, 1>(t, j) : j.variant == 2 ? go32<MODE, DIR, 4>(t, j)
-                                                                           : go32<MODE, DIR, 2>(t, j);
+        return u1 ? go32<MODE, DIR, 1>(t, j) : u4 ? go32<MODE, DIR, 4>(t, j) : go32<MODE, DIR, 2>(t, j);
     case 64:
         return go64<MODE, DIR>(t, j);
     default:
@@ -902,7 +954,9 @@ int mfma_supported(int rows, int cols, int precision)
 int mfma_variant_count(int rows, int cols, int, int precision)
 {
     if (!mfma_supported(rows, cols, precision)) return 0;
-    return rows == 64 ? 1 : rows == 32 ? 3 : 4; // unroll 2 / 1 / 4 (+ one-shot grid for 16x16 tiles)
+    // N < 64: unroll 2 / 1 / 4, one-shot grid, capped residency (N = 32: 3 = 1); N = 64:
+    // resident workgroups per CU as many as fit / two / one
+    return rows == 64 ? 3 : 8;
 }
 
 int launch_mfma(const DeviceTables* t, const Job& j, int precision)
