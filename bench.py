@@ -62,7 +62,8 @@ def parse():
     ap.add_argument("--load-policy", default="", help="freeze this saved policy instead of tuning")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch (one graph launch) measurement")
     ap.add_argument("--no-filter", action="store_true", help="skip the spectral-filter measurement")
-    ap.add_argument("--no-rect", action="store_true", help="skip the rectangle-orientation measurement")
+    ap.add_argument("--no-rect", action="store_true",
+                    help="skip the rectangle-orientation and long-axis (512, 1024) measurements")
     ap.add_argument("--no-c2", action="store_true", help="skip the C2 mixture timing")
     return ap.parse_args()
 
@@ -247,6 +248,7 @@ def main():
     # ---- the copy ceiling (library kernel, same run) ---------------------------------------
     copy_rows = copy_ceiling(dct, bufs[sizes[0]], stream, args.reps)
     copy_gbs = copy_rows["out_of_place"]["GB/s"]
+    valu = valu_ceiling(dct, stream)
 
     # ---- per-case statistics: 21 individually timed calls each -------------------------------
     per = {}
@@ -282,6 +284,7 @@ def main():
     filt = None if args.no_filter else filter_rates(dct, bufs, host, sizes, stream, per, args.reps)
     rect = None if args.no_rect else rect_rates(dct, bufs[sizes[0]], stream,
                                                 tune=not (args.no_tune or args.load_policy))
+    long_axes = None if args.no_rect else long_axis_rates(dct, bufs[sizes[0]], stream)
     ragged = None if args.no_ragged else ragged_c4(dct, stream, args.reps)
     del bufs
     torch.cuda.empty_cache()
@@ -295,9 +298,9 @@ def main():
                       "sizes": sizes, "batch": {str(n): int(host[n].shape[0]) for n in sizes},
                       "precision": args.precision, "variants": tuned},
            "hbm_frac": round(value / HBM_PEAK_GBS, 4), "copy_ceiling_GBps": round(copy_gbs, 1),
-           "copy": copy_rows, "wall_s": round(wall, 3), "self_check": checked,
+           "copy": copy_rows, "valu_ceiling": valu, "wall_s": round(wall, 3), "self_check": checked,
            "roofline": roofline, "per_size": per, "compare": compare, "c2_mixture": c2, "ragged_c4": ragged,
-           "filter": filt, "rectangles": rect}
+           "filter": filt, "rectangles": rect, "long_axes": long_axes}
 
     # ---- CPU baseline: the FP64 oracle timed on the host, and every row scored against it ------
     if not args.no_cpu:
@@ -401,7 +404,10 @@ def filter_rates(dct, bufs, host, sizes, stream, per, reps):
     return res
 
 
-RECT_PAIRS = ((8, 64), (64, 8), (16, 32), (32, 16), (8, 256), (256, 8), (64, 256), (256, 64))
+RECT_PAIRS = ((8, 64), (64, 8), (16, 32), (32, 16), (8, 256), (256, 8), (32, 256), (256, 32), (64, 256), (256, 64),
+              (128, 256), (256, 128))
+# shapes with an axis of 512 or 1024 (dense image passes behind the basic calls)
+LONG_SHAPES = ((512, 512), (1024, 1024), (8, 1024), (1024, 64))
 
 
 def rect_rates(dct, buf, stream, tune=True, reps=9):
@@ -427,6 +433,47 @@ def rect_rates(dct, buf, stream, tune=True, reps=9):
             res[key][d] = rate(8 * h * w * batch, ms, batch)
     del scratch
     torch.cuda.empty_cache()
+    return res
+
+
+def long_axis_rates(dct, buf, stream, reps=5):
+    """Axes of 512 and 1024 through the basic calls (dense image passes: one float32 product per
+    axis against Q_n), out of place on the same 2^27 floats; GB/s of 8 h w bytes per array.  Reported
+    beside the step, not part of it."""
+    import torch
+    res = {}
+    scratch = torch.empty_like(buf)
+    for h, w in LONG_SHAPES:
+        batch = buf.numel() // (h * w)
+        x = buf[:batch * h * w].view(batch, h, w)
+        y = scratch[:batch * h * w].view(batch, h, w)
+        key = "%dx%d" % (h, w)
+        res[key] = {}
+        for d in DIRS:
+            dct.transform(x, y, d, "fp32", stream=stream)
+            ms = time_calls(lambda i: dct.transform(x, y, d, "fp32", stream=stream), reps, stream)
+            res[key][d] = rate(8 * h * w * batch, ms, batch)
+    del scratch
+    torch.cuda.empty_cache()
+    return res
+
+
+def valu_ceiling(dct, stream, iters=4096):
+    """The vector-ALU issue reference (dct2d_fma_issue): independent float32 FMAs with 1, 2, 4 and 8
+    wavefronts per SIMD; wave64 instructions issued per SIMD and cycle (at the nominal 2.4 GHz) and the
+    FMA rate in TFLOP/s.  The VALU share of a kernel is judged against the rate at its occupancy."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    sink = torch.zeros(1, device="cuda")
+    res = {"cus": cus, "clock_GHz": 2.4, "iters": iters}
+    for w in (1, 2, 4, 8):
+        blocks = cus * w
+        dct.fma_issue(sink, blocks, 64, stream=stream)
+        ms = float(np.median(time_calls(lambda i: dct.fma_issue(sink, blocks, iters, stream=stream), 5, stream)))
+        instr = 16.0 * iters * 4 * blocks
+        per = instr / (ms * 1e-3 * 2.4e9 * cus * 4)
+        res["waves_per_simd_%d" % w] = {"ms": round(ms, 4), "instr_per_cycle_per_simd": round(per, 4),
+                                        "fma_TFLOPs": round(instr * 64 * 2 / (ms * 1e-3) / 1e12, 1)}
     return res
 
 
@@ -476,7 +523,7 @@ def kernel_name(n, d, tuned):
     return None
 
 
-KERNEL_SOURCES = ("kern_fp32.hip", "dct1d.hpp", "internal.hpp")
+KERNEL_SOURCES = ("kern_fp32.hip", "kern_rect256.hip", "fp32_common.hpp", "split256.hpp", "dct1d.hpp", "internal.hpp")
 
 
 def source_digest():
@@ -627,6 +674,20 @@ def score_all(dct, oracle, host, sizes, args, out, stream):
             batch = base.size // (h * w)
             x = base[:batch * h * w].reshape(batch, h, w)
             idx = spread(batch, 32, h * 7 + w)
+            xs = x[idx]
+            refs = _refs(oracle, xs)
+            for d in DIRS:
+                y = _sampled_output(dct, x, idx, d, "fp32", stream, False)
+                row[d]["e_rel"] = float("%.3e" % oracle.e_rel(y, refs[d], xs).max())
+        torch.cuda.empty_cache()
+    # axes of 512 and 1024 through the basic calls, out of place
+    if out.get("long_axes"):
+        base = host[sizes[0]].reshape(-1)
+        for key, row in out["long_axes"].items():
+            h, w = (int(v) for v in key.split("x"))
+            batch = base.size // (h * w)
+            x = base[:batch * h * w].reshape(batch, h, w)
+            idx = spread(batch, 6, h + 3 * w)
             xs = x[idx]
             refs = _refs(oracle, xs)
             for d in DIRS:

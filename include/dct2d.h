@@ -269,6 +269,16 @@ int dct2d_tune(int32_t rows, int32_t cols, int dir, int precision, int64_t batch
  * Errors: DCT2D_ERR_ARG (n < 0, null pointer with n > 0, overlap), DCT2D_ERR_ALIGN. */
 int dct2d_copy(const float* in, float* out, int64_t n, void* stream);
 
+/* Vector-ALU issue reference (measurement helper, no transform): launches `blocks`
+ * workgroups of 256 threads, each lane issuing iters x 16 independent float32 FMAs
+ * (wave64, no packed math).  With blocks = CUs x w the grid holds w wavefronts per SIMD;
+ * 16 x iters x 4 x blocks wavefront instructions over the elapsed time and the SIMD count
+ * give the FMA issue rate per SIMD and cycle at that occupancy, the reference for the VALU
+ * share of the transform kernels.  `sink`: a device float the kernel never writes in
+ * practice (the FMA results only feed a comparison that never holds).  Errors: DCT2D_ERR_ARG (null sink,
+ * blocks < 1, iters < 1), DCT2D_ERR_ALIGN. */
+int dct2d_fma_issue(float* sink, int32_t blocks, int32_t iters, void* stream);
+
 /* Human-readable text for a status code (static storage). */
 const char* dct2d_status_string(int status);
 

@@ -28,7 +28,7 @@ EXPORTS = ("dct2d_init", "dct2d_finalize", "dct2d_forward", "dct2d_inverse", "dc
            "dct2d_transform_ex", "dct2d_filter", "dct2d_ragged_plan_create", "dct2d_ragged_execute",
            "dct2d_ragged_plan_destroy", "dct2d_ragged_plan_info", "dct2d_variant_count",
            "dct2d_get_variant", "dct2d_set_variant", "dct2d_tune", "dct2d_status_string", "dct2d_version",
-           "dct2d_copy", "dct2d_image_transform", "dct2d_image_transform_noalloc")
+           "dct2d_copy", "dct2d_image_transform", "dct2d_image_transform_noalloc", "dct2d_fma_issue")
 
 
 class DCT2DError(RuntimeError):
@@ -71,6 +71,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dct2d_set_variant.argtypes = [i32, i32, c_int, c_int, c_int]
     lib.dct2d_tune.argtypes = [i32, i32, c_int, c_int, i64, vp, ctypes.POINTER(ctypes.c_float)]
     lib.dct2d_copy.argtypes = [vp, vp, i64, vp]
+    lib.dct2d_fma_issue.argtypes = [vp, i32, i32, vp]
     for n in ("dct2d_image_transform", "dct2d_image_transform_noalloc"):
         getattr(lib, n).argtypes = [c_int, vp, vp, i64, i32, i32, i64, i64, vp]
     lib.dct2d_status_string.argtypes = [c_int]
@@ -228,6 +229,17 @@ def copy(inp, out=None, stream=None):
     _check(load().dct2d_copy(ctypes.c_void_p(inp.data_ptr()), ctypes.c_void_p(out.data_ptr()), inp.numel(),
                              ctypes.c_void_p(_stream(stream))), "dct2d_copy")
     return out
+
+
+def fma_issue(sink, blocks, iters, stream=None):
+    """Launches the vector-ALU issue reference (dct2d_fma_issue): `blocks` workgroups of 256
+    threads, each lane issuing iters x 16 independent float32 FMAs.  sink: a float32 CUDA tensor
+    (never written in practice)."""
+    import torch
+    if sink.dtype != torch.float32 or not sink.is_cuda:
+        raise TypeError("float32 CUDA tensor required")
+    _check(load().dct2d_fma_issue(ctypes.c_void_p(sink.data_ptr()), int(blocks), int(iters),
+                                  ctypes.c_void_p(_stream(stream))), "dct2d_fma_issue")
 
 
 def _p(precision):

@@ -1,3 +1,6 @@
+// Reference kernels for the roofline figures (measurement helpers, not part of the
+// transforms).
+//
 // The library's reference copy: the practical HBM ceiling of a kernel that reads each
 // float32 element once and writes it once, as every transform here does.  Measured on
 // MI355X over 512 MiB (sweep of tile size, workgroup size and resident workgroups per
@@ -25,7 +28,35 @@ __global__ void __launch_bounds__(64) k_copy_tail(const float* in, float* out, i
     if (k < n) ((dct::gfloat*)out)[k] = ((const dct::gfloat*)in)[k];
 }
 
+// The vector-ALU issue reference: each lane runs `iters` rounds of 16 independent float32
+// FMAs (no dependency stalls past the first round), so the wall time of a grid with w
+// wavefronts per SIMD gives the wave64 FMA instructions a SIMD issues per cycle at that
+// occupancy.  The result only feeds a never-true comparison (nothing is stored).
+__global__ void __launch_bounds__(256) k_fma_issue(float* sink, int iters)
+{
+    float a[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) a[i] = threadIdx.x * 1e-3f + i;
+    const float b = 1.0000001f, c = 1e-7f;
+    for (int k = 0; k < iters; ++k) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a[i] = __builtin_fmaf(a[i], b, c);
+    }
+    float t = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t += a[i];
+    if (t == 1234.5f) ((dct::gfloat*)sink)[0] = t;
+}
+
 } // namespace
+
+extern "C" int dct2d_fma_issue(float* sink, int32_t blocks, int32_t iters, void* stream)
+{
+    if (!sink || blocks < 1 || iters < 1) return DCT2D_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(sink) & 3u) return DCT2D_ERR_ALIGN;
+    k_fma_issue<<<(unsigned)blocks, 256, 0, static_cast<hipStream_t>(stream)>>>(sink, iters);
+    return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
+}
 
 extern "C" int dct2d_copy(const float* in, float* out, int64_t n, void* stream)
 {

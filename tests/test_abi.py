@@ -59,6 +59,10 @@ def test_argument_validation_on_host():
     assert lib.dct2d_transform_ex(0, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x1100), 4, 8, 8, 64, 64, 0,
                                   None) == -1
     assert lib.dct2d_variant_count(26, 8, 0, 0) == 0
+    # measurement helpers reject bad arguments before any launch
+    assert lib.dct2d_fma_issue(None, 1, 1, None) == -1
+    assert lib.dct2d_fma_issue(ctypes.c_void_p(0x1000), 0, 1, None) == -1
+    assert lib.dct2d_fma_issue(ctypes.c_void_p(0x1002), 1, 1, None) == -4
     # axes of 512 and 1024: float32 path only; no variants, tuner or filter
     assert lib.dct2d_transform_ex(0, None, None, 0, 512, 512, 512 * 512, 512 * 512, 4, None) == -5
     assert lib.dct2d_transform_ex(1, None, None, 0, 1024, 64, 1024 * 64, 1024 * 64, 7, None) == 0
