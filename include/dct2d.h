@@ -32,9 +32,12 @@
  *
  * Sizes accepted by the three basic calls and dct2d_transform_ex: rows and cols each
  * a power of two in [8, 1024] (squares and rectangles).  Axes up to 256 run the fused
- * kernels; a shape with an axis of 512 or 1024 runs the dense image passes of
- * dct2d_image_transform (one float32 product per axis against Q_n, a workspace of one
- * image per image taken from the stream-ordered allocator on `stream`), on the float32
+ * kernels; a shape with an axis of 512 or 1024 runs two line passes, rows then columns,
+ * the second in place on `out` (no workspace, no allocation): a 512- or 1024-point line is
+ * split into its even/odd halves (Section 2.2) down to length-256 DCT-II/III and DCT-IV
+ * transforms (the DCT-IV of a 512-point half through a 128-point complex FFT), each half
+ * held by one wavefront and the halves combined through LDS.  Each pass reads and writes
+ * the array once (the round trip of a 1024 axis: forward then inverse, two passes).  Float32
  * path only (any other precision: DCT2D_ERR_PRECISION).  The variant, autotuner and
  * filter calls cover axes up to 256.  Any other length returns DCT2D_ERR_SIZE: like the
  * paper (Section 7.1) the basic API rejects non-power-of-two axes instead of
@@ -165,7 +168,8 @@ int dct2d_filter(const float* in, float* out, int64_t batch, int32_t rows, int32
  * both axes in [8, 1024] and cols a multiple of 4, including lengths that are not powers of
  * two (384, 600, 1000, ...): the strided-batch form of the ragged planner's image classes.
  * Pointers, strides, alignment and in-place rules as dct2d_transform_ex.  Shapes with both
- * axes powers of two up to 256 run the basic calls' kernels (DCT2D_AUTO).  Every other shape
+ * axes powers of two run the basic calls' kernels (DCT2D_AUTO; with an axis of 512 or 1024
+ * the two line passes, which use no workspace).  Every other shape
  * is computed exactly from the dense Q_n of eq. 1 (Section 2.1; the paper's own library
  * rejects non-power-of-two axes, Section 7.1, rather than zero-padding them, which would
  * change the transform): one dense float32 product per axis (two for the round trip), with
@@ -185,8 +189,9 @@ int dct2d_image_transform(int dir, const float* in, float* out, int64_t batch, i
  * (DCT2D_ERR_NOINIT otherwise).  The dense Q tables and the workspace live in a fixed
  * 64 MiB device array that the library holds on every device it runs on until the process
  * ends; the tables are rebuilt in it on `stream` by every call and the batch is processed in
- * chunks that fit (every accepted shape fits: 1024 x 1024 needs 12 MiB for one image), so
- * results equal dct2d_image_transform's.  Calls on one device share that array: calls that
+ * chunks that fit (every accepted shape fits: the largest, 1024 x 1020, needs 12 MiB for one
+ * image), so results equal dct2d_image_transform's.  Shapes whose axes are both powers of
+ * two use none of the array (the basic calls' kernels, no tables, no workspace).  Calls on one device share that array: calls that
  * overlap in time on one device (different streams, or threads without ordering) race and
  * give wrong results.  Same arguments and errors as dct2d_image_transform, except that
  * DCT2D_ERR_SIZE also marks a shape needing more than the 64 MiB (none of the accepted
@@ -199,9 +204,11 @@ int dct2d_image_transform_noalloc(int dir, const float* in, float* out, int64_t 
  * A descriptor names one array inside a caller buffer: its first element is at
  * base + offset (floats), its shape rows x cols (pitch = cols).  Arrays must not
  * overlap.  Accepted shapes: both axes in [8, 1024] with cols a multiple of 4; shapes
- * with both axes powers of two <= 256 use the fast kernels of the basic calls, any
- * other shape (whole images such as 1024 x 1024 or 512 x 384) is computed with dense
- * float32 Q_n tables (exact for non-power-of-two axes; no zero-padding).
+ * with both axes powers of two <= 256 use the fast kernels of the basic calls, shapes
+ * with both axes powers of two and one of 512 or 1024 (1024 x 1024, 64 x 1024) the two
+ * float32 line passes of the basic calls, in place (whatever the plan's precision), and
+ * any other shape (512 x 384) is computed with dense float32 Q_n tables (exact for
+ * non-power-of-two axes; no zero-padding).
  *
  * dct2d_ragged_plan_create copies the (host) descriptor array, groups the items into
  * shape classes, uploads the per-class offset lists to the device, picks each class's

@@ -16,7 +16,7 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libdct2d.so")
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ("tables.hip", "kern_fp32.hip", "kern_mfma.hip", "kern_dense.hip", "ragged.cpp", "capi.cpp", "ceiling.hip", "image.hip", "kern_rect256.hip")
+SOURCES = ("tables.hip", "kern_fp32.hip", "kern_mfma.hip", "kern_dense.hip", "ragged.cpp", "capi.cpp", "ceiling.hip", "image.hip", "kern_rect256.hip", "kern_long.hip")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           # packed FP32 VALU forms stay disabled (the compiler is free to use scalar FMA)

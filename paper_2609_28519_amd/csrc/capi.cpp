@@ -53,8 +53,8 @@ bool basic_size_ok(int rows, int cols)
 }
 
 // Power-of-two shapes with an axis of 512 or 1024 (the other 8 .. 1024): accepted by the
-// transform calls and computed by the dense image passes (one product per axis against the
-// FP64-built Q_n, float32); no kernel variants, float32 path only.
+// transform calls and computed by two passes over HBM whose long-axis lines are shared by two
+// or four wavefronts (kern_long.hip); no kernel variants, float32 path only.
 bool long_axis_size_ok(int rows, int cols)
 {
     return is_pow2(rows) && is_pow2(cols) && rows >= 8 && rows <= 1024 && cols >= 8 && cols <= 1024 &&
@@ -121,14 +121,12 @@ int run(int dir, const float* in, float* out, int64_t batch, int32_t rows, int32
 {
     int rc = validate(dir, in, out, batch, rows, cols, in_stride, out_stride, prec);
     if (rc != DCT2D_OK) return rc;
-    if (long_axis_size_ok(rows, cols)) {
-        if (prec != DCT2D_FP32 && prec != DCT2D_AUTO) return DCT2D_ERR_PRECISION;
-        return dct2d_image_transform(dir, in, out, batch, rows, cols, in_stride, out_stride, stream);
-    }
+    if (long_axis_size_ok(rows, cols) && prec != DCT2D_FP32 && prec != DCT2D_AUTO) return DCT2D_ERR_PRECISION;
     if (batch == 0) return rc;
     const DeviceTables* t = tables_current(&rc);
     if (!t) return rc;
     Job j{dir, in, out, batch, rows, cols, in_stride, out_stride, static_cast<hipStream_t>(stream), 0};
+    if (long_axis_size_ok(rows, cols)) return launch_long(t, j);
     return dispatch(t, j, prec);
 }
 

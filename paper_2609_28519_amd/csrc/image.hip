@@ -1,11 +1,11 @@
 // Batched transforms of whole images of any shape with both axes in [8, 1024] (columns a
 // multiple of 4): the strided-batch counterpart of the ragged planner's image classes.
 //
-// Shapes whose axes are both powers of two up to 256 go to the fast kernels of the basic
-// calls (the frozen float32-accurate path).  Every other shape (512, 1024, and axes that
-// are not powers of two, such as 384 or 600) is computed exactly from the dense Q_n of
-// eq. 1 (FP64-generated, rounded to float32; no zero-padding), one dense product per axis
-// (kern_dense.hip).  A dense pass writes its output tile from whole input rows or
+// Shapes whose axes are both powers of two go to the kernels of the basic calls: up to 256
+// the frozen float32-accurate path, with an axis of 512 or 1024 the two-pass long-axis
+// kernels (kern_long.hip, no workspace).  Every other shape (axes that are not powers of
+// two, such as 384 or 600) is computed exactly from the dense Q_n of eq. 1 (FP64-generated,
+// rounded to float32; no zero-padding), one dense product per axis (kern_dense.hip).  A dense pass writes its output tile from whole input rows or
 // columns, so the two (round trip: four) passes ping-pong through a workspace of one
 // float32 image per image of the batch:
 //   forward / inverse   in -> ws (row pass, Q_cols)       ws -> out (column pass, Q_rows)
@@ -32,8 +32,9 @@ namespace {
 // ---- the no-allocation scratch ---------------------------------------------------------
 // 64 MiB per device, held from the library's load until the process ends.  Layout per
 // call: dense Q_rows, then Q_cols (when cols != rows), then the workspace, each region
-// 256-byte aligned.  The largest shape (1024 x 1024) needs 2 x 4 MiB of tables and 4 MiB
-// per image of workspace, so every accepted shape fits at least one image per chunk.
+// 256-byte aligned.  The largest dense shape (1024 x 1020) needs 2 x 4 MiB of tables and
+// 4 MiB per image of workspace, so every accepted shape fits at least one image per chunk
+// (power-of-two shapes, 1024 x 1024 included, do not use the scratch).
 constexpr size_t kScratchBytes = size_t(64) << 20;
 __device__ __align__(256) float scratch[kScratchBytes / sizeof(float)];
 
@@ -47,6 +48,8 @@ std::map<std::pair<int, int>, float*> g_q;
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 bool fast_shape(int r, int c) { return is_pow2(r) && is_pow2(c) && r >= 8 && r <= 256 && c >= 8 && c <= 256; }
+// power-of-two shapes with an axis of 512 or 1024: the two-pass long-axis kernels (no workspace)
+bool long_shape(int r, int c) { return is_pow2(r) && is_pow2(c) && r >= 8 && c >= 8 && r <= 1024 && c <= 1024 && (r > 256 || c > 256); }
 
 int validate(int dir, const float* in, const float* out, int64_t batch, int rows, int cols, int64_t in_stride,
              int64_t out_stride)
@@ -179,6 +182,10 @@ int dct2d_image_transform(int dir, const float* in, float* out, int64_t batch, i
         Job j{dir, in, out, batch, rows, cols, in_stride, out_stride, s, 0};
         return dispatch(t, j, DCT2D_AUTO);
     }
+    if (long_shape(rows, cols)) {
+        Job j{dir, in, out, batch, rows, cols, in_stride, out_stride, s, 0};
+        return launch_long(t, j);
+    }
     const float* q_rows = cached_q(t->device, rows, &rc);
     const float* q_cols = q_rows ? cached_q(t->device, cols, &rc) : nullptr;
     if (!q_rows || !q_cols) return rc;
@@ -208,6 +215,10 @@ int dct2d_image_transform_noalloc(int dir, const float* in, float* out, int64_t 
     if (fast_shape(rows, cols)) {
         Job j{dir, in, out, batch, rows, cols, in_stride, out_stride, s, 0};
         return dispatch(t, j, DCT2D_AUTO);
+    }
+    if (long_shape(rows, cols)) {
+        Job j{dir, in, out, batch, rows, cols, in_stride, out_stride, s, 0};
+        return launch_long(t, j);
     }
     float* base = scratch_ptr(&rc);
     if (!base) return rc;

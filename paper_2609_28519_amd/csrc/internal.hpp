@@ -164,6 +164,13 @@ int launch_dense_axis(const Addr& a, int64_t count, int rows, int cols, bool col
                       const float* q, hipStream_t s);
 
 int launch_fp32(const DeviceTables* t, const Job& j);
+// One pass of direction `dir` along the rows (or, column_pass, the columns) of length
+// len <= 256 of `batch` arrays with lines_per_array lines each, one thread per line.
+int launch_short_line_pass(const DeviceTables* t, const Addr& a, int64_t batch, int len, int lines_per_array,
+                           bool column_pass, int dir, hipStream_t s);
+// Power-of-two shapes with an axis of 512 or 1024, the other 8 .. 1024 (kern_long.hip): a row
+// pass and a column pass, the second in place on the output.
+int launch_long(const DeviceTables* t, const Job& j);
 // Rectangles with one axis of 256 and the other at most 128, fused (kern_rect256.hip).
 int launch_rect256(const DeviceTables* t, const Job& j);
 int fp32_variant_count(int rows, int cols, int dir);

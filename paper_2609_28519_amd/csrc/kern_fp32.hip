@@ -1603,6 +1603,28 @@ int cols_any(const DeviceTables* t, int len, const Addr& a, int64_t batch, int c
     return hipGetLastError() == hipSuccess ? DCT2D_OK : DCT2D_ERR_HIP;
 }
 
+} // namespace
+
+int launch_short_line_pass(const DeviceTables* t, const Addr& a, int64_t batch, int len, int lines_per_array,
+                           bool column_pass, int dir, hipStream_t s)
+{
+    switch (dir) {
+    case DCT2D_FORWARD:
+        return column_pass ? cols_any<DCT2D_FORWARD>(t, len, a, batch, lines_per_array, s)
+                           : rows_any<DCT2D_FORWARD>(t, len, a, batch, lines_per_array, s);
+    case DCT2D_INVERSE:
+        return column_pass ? cols_any<DCT2D_INVERSE>(t, len, a, batch, lines_per_array, s)
+                           : rows_any<DCT2D_INVERSE>(t, len, a, batch, lines_per_array, s);
+    case DCT2D_ROUNDTRIP:
+        return column_pass ? cols_any<DCT2D_ROUNDTRIP>(t, len, a, batch, lines_per_array, s)
+                           : rows_any<DCT2D_ROUNDTRIP>(t, len, a, batch, lines_per_array, s);
+    default:
+        return DCT2D_ERR_ARG;
+    }
+}
+
+namespace {
+
 // Two-pass schedule over HBM (rows, then columns; the round trip needs a third pass).
 // The first pass reads the input arrays and writes the output arrays; the later
 // passes work in place on the output arrays.

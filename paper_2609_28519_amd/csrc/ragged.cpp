@@ -6,8 +6,9 @@
 // configuration of the frozen per-size policy (the same table the autotuner fills for
 // the basic calls, Section 3.2: variants fixed before measurement), with grid-stride
 // schedules replaced by one tile per workgroup, since the classes share the GPU.  Image classes
-// whose axes the fast transforms do not cover (non-powers of two such as 384, or axes
-// above 256) get dense float32 Q tables and a workspace.  The whole batch is then
+// with power-of-two axes and an axis of 512 or 1024 run the two-pass long-axis kernels in
+// place on the batch (no workspace); image classes with an axis that is not a power of two
+// (such as 384) get dense float32 Q tables and a workspace.  The whole batch is then
 // recorded once into a HIP graph: one fork-join branch per class, so independent
 // classes run concurrently.  Kernels read the batch base pointer from a plan-owned
 // device slot, so the recorded graph replays on any buffer.
@@ -33,6 +34,7 @@ struct ClassRec {
     int64_t count;
     int64_t* d_off = nullptr; // device offsets (floats from base)
     bool dense = false;       // dense axis passes through the workspace
+    bool long_axes = false;   // two-pass long-axis kernels (an axis of 512 or 1024)
     float* q_rows = nullptr;  // dense Q_rows (column pass)
     float* q_cols = nullptr;  // dense Q_cols (row pass)
     float* ws = nullptr;      // workspace, count * rows * cols floats
@@ -42,6 +44,13 @@ bool fast_shape(int r, int c)
 {
     return is_pow2(r) && is_pow2(c) && r >= 8 && r <= 256 && c >= 8 && c <= 256;
 }
+
+bool long_shape(int r, int c)
+{
+    return is_pow2(r) && is_pow2(c) && r >= 8 && c >= 8 && r <= 1024 && c <= 1024 && (r > 256 || c > 256);
+}
+
+bool dense_shape(int r, int c) { return !fast_shape(r, c) && !long_shape(r, c); }
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -91,6 +100,8 @@ int record_class(const DeviceTables* t, dct2d_ragged_plan* p, const ClassRec& c,
         j.in_idx = j.out_idx = c.d_off;
         j.in_slot = j.out_slot = p->d_slot;
         j.shared = true; // the classes run as concurrent branches of the graph
+        // long axes: float32 whatever the plan's precision (the split paths cover axes <= 256)
+        if (c.long_axes) return launch_long(t, j);
         return dispatch(t, j, p->prec);
     }
     // dense image passes: base(indexed) <-> workspace(packed), ping-pong
@@ -168,7 +179,7 @@ int dct2d_ragged_plan_create(const dct2d_block* blocks, int64_t count, int dir, 
     std::map<int, size_t> qoff;
     for (auto& g : groups) bytes = align256(bytes + g.second.size() * sizeof(int64_t));
     for (auto& g : groups) {
-        if (fast_shape(g.first.first, g.first.second)) continue;
+        if (!dense_shape(g.first.first, g.first.second)) continue;
         for (int L : {g.first.first, g.first.second})
             if (!qoff.count(L)) {
                 qoff[L] = bytes;
@@ -177,7 +188,7 @@ int dct2d_ragged_plan_create(const dct2d_block* blocks, int64_t count, int dir, 
     }
     std::vector<size_t> wsoff;
     for (auto& g : groups) {
-        if (fast_shape(g.first.first, g.first.second)) {
+        if (!dense_shape(g.first.first, g.first.second)) {
             wsoff.push_back(0);
             continue;
         }
@@ -205,7 +216,8 @@ int dct2d_ragged_plan_create(const dct2d_block* blocks, int64_t count, int dir, 
             release(p);
             return DCT2D_ERR_HIP;
         }
-        if (!fast_shape(c.rows, c.cols)) {
+        c.long_axes = long_shape(c.rows, c.cols);
+        if (dense_shape(c.rows, c.cols)) {
             c.dense = true;
             c.q_rows = reinterpret_cast<float*>(base + qoff[c.rows]);
             c.q_cols = reinterpret_cast<float*>(base + qoff[c.cols]);

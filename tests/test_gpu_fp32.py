@@ -65,20 +65,40 @@ def test_rectangles(h, w, direction):
     assert_parity(x, y, direction, label="%dx%d" % (h, w))
 
 
-@pytest.mark.parametrize("h,w", [(512, 512), (1024, 1024), (8, 1024), (1024, 16), (256, 512), (512, 64)])
+LONG_SHAPES = [(512, 512), (1024, 1024), (8, 1024), (1024, 8), (1024, 16), (16, 512), (256, 512), (512, 64),
+               (512, 1024), (1024, 512), (128, 1024)]
+
+
+@pytest.mark.parametrize("h,w", LONG_SHAPES)
 @pytest.mark.parametrize("direction", DIRS)
 def test_long_axes_basic_calls(h, w, direction):
-    """Axes of 512 and 1024 through the in-place basic calls (dense image passes behind them):
-    several arrays, every one checked against the oracle."""
+    """Axes of 512 and 1024 through the in-place basic calls (two passes whose long-axis lines
+    are shared by two or four wavefronts): a batch whose line count leaves a partial group of 64
+    lines, every array checked against the oracle."""
     import torch
     dct = _lib()
     g = np.random.default_rng(h + 7 * w)
-    batch = max(2, min(9, (1 << 22) // (h * w)))
+    batch = max(3, min(9, (1 << 22) // (h * w)))
     x = g.standard_normal((batch, h, w)).astype(np.float32)
     t = to_gpu(x)
     {"forward": dct.forward_, "inverse": dct.inverse_, "roundtrip": dct.roundtrip_}[direction](t)
     torch.cuda.synchronize()
     assert_parity(x, t.cpu().numpy(), direction, label="%dx%d" % (h, w))
+
+
+@pytest.mark.parametrize("h,w", [(512, 512), (8, 1024), (1024, 64)])
+@pytest.mark.parametrize("direction", DIRS)
+def test_long_axes_out_of_place(h, w, direction):
+    """The same out of place: the input is left untouched and the output matches the oracle."""
+    import torch
+    dct = _lib()
+    g = np.random.default_rng(3 * h + w)
+    x = g.standard_normal((5, h, w)).astype(np.float32)
+    t = to_gpu(x)
+    out = dct.transform(t, None, direction, "fp32")
+    torch.cuda.synchronize()
+    assert np.array_equal(t.cpu().numpy(), x), "out-of-place call modified its input"
+    assert_parity(x, out.cpu().numpy(), direction, label="%dx%d" % (h, w))
 
 
 def test_long_axes_other_precisions_rejected():
