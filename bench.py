@@ -406,8 +406,8 @@ def filter_rates(dct, bufs, host, sizes, stream, per, reps):
 
 RECT_PAIRS = ((8, 64), (64, 8), (16, 32), (32, 16), (8, 256), (256, 8), (32, 256), (256, 32), (64, 256), (256, 64),
               (128, 256), (256, 128))
-# shapes with an axis of 512 or 1024 (dense image passes behind the basic calls)
-LONG_SHAPES = ((512, 512), (1024, 1024), (8, 1024), (1024, 64))
+# shapes with an axis of 512 or 1024 (the two-pass long-axis kernels behind the basic calls)
+LONG_SHAPES = ((512, 512), (1024, 1024), (8, 1024), (1024, 64), (512, 64), (64, 512))
 
 
 def rect_rates(dct, buf, stream, tune=True, reps=9):
@@ -437,9 +437,9 @@ def rect_rates(dct, buf, stream, tune=True, reps=9):
 
 
 def long_axis_rates(dct, buf, stream, reps=5):
-    """Axes of 512 and 1024 through the basic calls (dense image passes: one float32 product per
-    axis against Q_n), out of place on the same 2^27 floats; GB/s of 8 h w bytes per array.  Reported
-    beside the step, not part of it."""
+    """Axes of 512 and 1024 through the basic calls (a row pass and an in-place column pass of the
+    long-axis kernels; an axis <= 256 of such a shape runs the short line passes), out of place on
+    the same 2^27 floats; GB/s of 8 h w bytes per array.  Reported beside the step, not part of it."""
     import torch
     res = {}
     scratch = torch.empty_like(buf)
