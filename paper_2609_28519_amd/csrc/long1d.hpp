@@ -27,6 +27,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "dct1d.hpp"
 
 namespace dct {
@@ -79,19 +81,27 @@ __host__ __device__ __forceinline__ void chunk_fence(const A& a)
 // would be a full memory round trip, and without the pins the compiler would keep every
 // loaded value of the line live at once.  The accessor's base pointer is re-read before each
 // chunk (refresh), so the addresses of later chunks are not computed ahead and held live.
+// The chunk sequence is unrolled at compile time (c is an integral_constant): a runtime loop
+// over chunks would index the line's value array dynamically and put it in scratch memory.
+template <int C0, int K, class Buf, class A, class Load, class Use>
+__host__ __device__ __forceinline__ void pipelined_from(const A& x, Buf (&buf)[2], Load& load, Use& use)
+{
+    if constexpr (C0 < K) {
+        if constexpr (C0 + 1 < K) {
+            x.refresh();
+            load(std::integral_constant<int, C0 + 1>{}, buf[(C0 + 1) & 1]);
+        }
+        use(std::integral_constant<int, C0>{}, buf[C0 & 1]);
+        pipelined_from<C0 + 1, K>(x, buf, load, use);
+    }
+}
+
 template <int K, class Buf, class A, class Load, class Use>
 __host__ __device__ __forceinline__ void pipelined(const A& x, Load&& load, Use&& use)
 {
     Buf buf[2];
-    load(0, buf[0]);
-#pragma unroll
-    for (int c = 0; c < K; ++c) {
-        if (c + 1 < K) {
-            x.refresh();
-            load(c + 1, buf[(c + 1) & 1]);
-        }
-        use(c, buf[c & 1]);
-    }
+    load(std::integral_constant<int, 0>{}, buf[0]);
+    pipelined_from<0, K>(x, buf, load, use);
 }
 
 template <int N>
@@ -114,14 +124,16 @@ __host__ __device__ __forceinline__ void fwd512_in(const A& x, float (&v)[256])
         constexpr int C = 8;
         pipelined<64 / C, F4s<2 * C>>(
             x,
-            [&](int c, F4s<2 * C>& b) {
+            [&](auto cc, F4s<2 * C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     b.q[2 * i] = x.g4(c * C + i);
                     b.q[2 * i + 1] = x.g4(127 - c * C - i);
                 }
             },
-            [&](int c, const F4s<2 * C>& b) {
+            [&](auto cc, const F4s<2 * C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     const int g = c * C + i;
@@ -137,14 +149,16 @@ __host__ __device__ __forceinline__ void fwd512_in(const A& x, float (&v)[256])
         constexpr int C = 16; // values: x[n], x[511-n]
         pipelined<256 / C, Fs<2 * C>>(
             x,
-            [&](int c, Fs<2 * C>& b) {
+            [&](auto cc, Fs<2 * C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     b.f[2 * i] = x.at(c * C + i);
                     b.f[2 * i + 1] = x.at(511 - c * C - i);
                 }
             },
-            [&](int c, const Fs<2 * C>& b) {
+            [&](auto cc, const Fs<2 * C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     const int n = c * C + i;
@@ -164,7 +178,8 @@ __host__ __device__ __forceinline__ void fwd1024_in01(const A& x, float (&v)[256
         constexpr int C = 4;
         pipelined<64 / C, F4s<4 * C>>(
             x,
-            [&](int c, F4s<4 * C>& b) {
+            [&](auto cc, F4s<4 * C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     const int g = c * C + i;
@@ -174,7 +189,8 @@ __host__ __device__ __forceinline__ void fwd1024_in01(const A& x, float (&v)[256
                     b.q[4 * i + 3] = x.g4(128 + g);
                 }
             },
-            [&](int c, const F4s<4 * C>& b) {
+            [&](auto cc, const F4s<4 * C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     const int g = c * C + i;
@@ -191,7 +207,8 @@ __host__ __device__ __forceinline__ void fwd1024_in01(const A& x, float (&v)[256
         constexpr int C = 8; // values: x[n], x[1023-n], x[511-n], x[512+n]
         pipelined<256 / C, Fs<4 * C>>(
             x,
-            [&](int c, Fs<4 * C>& b) {
+            [&](auto cc, Fs<4 * C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     const int n = c * C + i;
@@ -201,7 +218,8 @@ __host__ __device__ __forceinline__ void fwd1024_in01(const A& x, float (&v)[256
                     b.f[4 * i + 3] = x.at(512 + n);
                 }
             },
-            [&](int c, const Fs<4 * C>& b) {
+            [&](auto cc, const Fs<4 * C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     const int n = c * C + i;
@@ -231,7 +249,8 @@ __host__ __device__ __forceinline__ void fwd1024_in23(const A& x, cf (&t)[128], 
         constexpr int C = 4;
         pipelined<64 / C, F4s<4 * C>>(
             x,
-            [&](int c, F4s<4 * C>& b) {
+            [&](auto cc, F4s<4 * C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
                 for (int k = 0; k < C; ++k) {
                     const int i = c * C + k;
@@ -241,7 +260,8 @@ __host__ __device__ __forceinline__ void fwd1024_in23(const A& x, cf (&t)[128], 
                     b.q[4 * k + 3] = x.g4(128 + i);
                 }
             },
-            [&](int c, const F4s<4 * C>& b) {
+            [&](auto cc, const F4s<4 * C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
                 for (int k = 0; k < C; ++k) {
                     const int i = c * C + k;
@@ -256,25 +276,40 @@ __host__ __device__ __forceinline__ void fwd1024_in23(const A& x, cf (&t)[128], 
                 }
             });
     } else {
-        constexpr int C = 8; // points: x[m], x[1023-m], x[511-m], x[512+m] with m = 2n' = 4i + e
-        pipelined<128 / C, Fs<4 * C>>(
+        // steps j: points j and 127 - j, whose rows are the four quadruples {n, 1023-n, 511-n,
+        // 512+n} with n = 4j + e and n = 4j + 3 - e, the rows that parts 0 and 1 read for their
+        // values 4j .. 4j+3: two steps per chunk keep the four parts on the same rows (cache
+        // lines shared through L2) chunk by chunk.
+        constexpr int C = 2;
+        pipelined<64 / C, Fs<8 * C>>(
             x,
-            [&](int c, Fs<4 * C>& b) {
+            [&](auto cc, Fs<8 * C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
                 for (int k = 0; k < C; ++k) {
-                    const int m = 4 * (c * C + k) + e;
-                    b.f[4 * k] = x.at(m);
-                    b.f[4 * k + 1] = x.at(1023 - m);
-                    b.f[4 * k + 2] = x.at(511 - m);
-                    b.f[4 * k + 3] = x.at(512 + m);
+                    const int j = c * C + k;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int m = 4 * (h ? 127 - j : j) + e;
+                        b.f[8 * k + 4 * h] = x.at(m);
+                        b.f[8 * k + 4 * h + 1] = x.at(1023 - m);
+                        b.f[8 * k + 4 * h + 2] = x.at(511 - m);
+                        b.f[8 * k + 4 * h + 3] = x.at(512 + m);
+                    }
                 }
             },
-            [&](int c, const Fs<4 * C>& b) {
+            [&](auto cc, const Fs<8 * C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
                 for (int k = 0; k < C; ++k) {
-                    const int i = c * C + k;
-                    t[i] = pre512<P>(b.f[4 * k] - b.f[4 * k + 1], b.f[4 * k + 2] - b.f[4 * k + 3], i, tw);
-                    pin(t[i]);
+                    const int j = c * C + k;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int i = h ? 127 - j : j;
+                        const float* f = b.f + 8 * k + 4 * h;
+                        t[i] = pre512<P>(f[0] - f[1], f[2] - f[3], i, tw);
+                        pin(t[i]);
+                    }
                 }
             });
     }
@@ -290,11 +325,13 @@ __host__ __device__ __forceinline__ void inv512_in(const A& X, float (&v)[256])
         constexpr int C = 16; // groups X[4g .. 4g+3]: X[4g+P] = v[2g], X[4g+2+P] = v[2g+1]
         pipelined<128 / C, F4s<C>>(
             X,
-            [&](int c, F4s<C>& b) {
+            [&](auto cc, F4s<C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
                 for (int i = 0; i < C; ++i) b.q[i] = X.g4(c * C + i);
             },
-            [&](int c, const F4s<C>& b) {
+            [&](auto cc, const F4s<C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     const int g = c * C + i;
@@ -308,11 +345,13 @@ __host__ __device__ __forceinline__ void inv512_in(const A& X, float (&v)[256])
         constexpr int C = 32;
         pipelined<256 / C, Fs<C>>(
             X,
-            [&](int c, Fs<C>& b) {
+            [&](auto cc, Fs<C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
                 for (int i = 0; i < C; ++i) b.f[i] = X.at(2 * (c * C + i) + P);
             },
-            [&](int c, const Fs<C>& b) {
+            [&](auto cc, const Fs<C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     v[c * C + i] = b.f[i];
@@ -326,22 +365,28 @@ __host__ __device__ __forceinline__ void inv512_in(const A& X, float (&v)[256])
 template <int P, class A>
 __host__ __device__ __forceinline__ void inv1024_in01(const A& X, float (&v)[256])
 {
-    constexpr int C = 32;
-    pipelined<256 / C, Fs<C>>(
+    // chunk c: k in [16c, 16c + 16) and [240 - 16c, 256 - 16c), the float4 groups that parts 2
+    // and 3 read in their chunk c, so that a row's cache lines serve all four parts close
+    // together in time (otherwise the back half of the row is fetched again from HBM)
+    constexpr int C = 16;
+    auto kk = [](int c, int i) { return i < C ? c * C + i : 256 - (c + 1) * C + (i - C); };
+    pipelined<256 / (2 * C), Fs<2 * C>>(
         X,
-        [&](int c, Fs<C>& b) {
+        [&](auto cc, Fs<2 * C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
-            for (int i = 0; i < C; ++i) {
-                const int k = c * C + i;
+            for (int i = 0; i < 2 * C; ++i) {
+                const int k = kk(c, i);
                 if constexpr (A::VEC) b.f[i] = e4(X.g4(k), 2 * P);
                 else b.f[i] = X.at(4 * k + 2 * P);
             }
         },
-        [&](int c, const Fs<C>& b) {
+        [&](auto cc, const Fs<2 * C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
-            for (int i = 0; i < C; ++i) {
-                v[c * C + i] = b.f[i];
-                pin(v[c * C + i]);
+            for (int i = 0; i < 2 * C; ++i) {
+                v[kk(c, i)] = b.f[i];
+                pin(v[kk(c, i)]);
             }
         });
 }
@@ -351,10 +396,13 @@ __host__ __device__ __forceinline__ void inv1024_in01(const A& X, float (&v)[256
 template <int P, class A>
 __host__ __device__ __forceinline__ void inv1024_in23(const A& X, cf (&t)[128], twptr tw)
 {
-    constexpr int C = 16;
+    // chunk c: points i in [8c, 8c + 8), reading float4 groups [16c, 16c + 16) (yo[2n']) and
+    // [240 - 16c, 256 - 16c) (yo[511-2n']), the groups of parts 0 and 1's chunk c
+    constexpr int C = 8;
     pipelined<128 / C, Fs<2 * C>>(
         X,
-        [&](int c, Fs<2 * C>& b) {
+        [&](auto cc, Fs<2 * C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
             for (int k = 0; k < C; ++k) {
                 const int j = 4 * (c * C + k) + 2 * (P - 2);       // 2n'
@@ -368,7 +416,8 @@ __host__ __device__ __forceinline__ void inv1024_in23(const A& X, cf (&t)[128], 
                 }
             }
         },
-        [&](int c, const Fs<2 * C>& b) {
+        [&](auto cc, const Fs<2 * C>& b) {
+                constexpr int c = decltype(cc)::value;
 #pragma unroll
             for (int k = 0; k < C; ++k) {
                 const int i = c * C + k;
