@@ -153,7 +153,7 @@ __device__ __forceinline__ void part512(const A& in, const Out& o, float* lds, i
 template <int P>
 __device__ __forceinline__ void dct4_512_exchange(const cf (&t)[128], float (&y)[256], float* lds, int lane, twptr tw)
 {
-    cf f[128], pf[128];
+    cf f[128];
     lng::dct4_512_fft<P>(t, f, tw);
     constexpr int own = P == 2 ? 0 : 256, other = P == 2 ? 256 : 0;
 #pragma unroll
@@ -162,9 +162,17 @@ __device__ __forceinline__ void dct4_512_exchange(const cf (&t)[128], float (&y)
         ld(lds, own + 2 * k + 1, lane) = f[k].y;
     }
     __syncthreads();
+    // the partner's half is read chunk by chunk as the post-twiddle consumes it, and the twiddle
+    // pointer is fenced here, so neither the 256 partner values nor the post twiddles are loaded
+    // early and held beside f (they would be spilled)
+    twptr twp = tw;
+    tw_fence(twp);
 #pragma unroll
-    for (int k = 0; k < 128; ++k) pf[k] = cf{ld(lds, other + 2 * k, lane), ld(lds, other + 2 * k + 1, lane)};
-    lng::dct4_512_post<P>(f, pf, y, tw);
+    for (int k = 0; k < 128; ++k) {
+        const cf pf{ld(lds, other + 2 * k, lane), ld(lds, other + 2 * k + 1, lane)};
+        lng::dct4_512_post_k<P>(f[k], pf, k, y, twp);
+        if ((k & 15) == 15) lng::chunk_fence();
+    }
 }
 
 template <int DIR, bool COLS, int P, class A>
@@ -222,8 +230,10 @@ __device__ __forceinline__ void part1024(const A& in, const Out& o, float* lds, 
         // x[n] = u + w[n], x[1023-n] = u - w[n], x[511-n] = u' + w[511-n], x[512+n] = u' - w[511-n]
         // with u = uu + uw, u' = uu - uw, over n in [128 r, 128 r + 128): LDS rows [0, 128) uu,
         // [128, 256) uw, [256, 384) w[n], [384, 512) w[511-n]
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        // the two rounds are separate instantiations (r a compile-time constant): as a loop the
+        // compiler would keep it rolled and index y at run time, which puts y in scratch
+        auto round = [&](auto rc) {
+            constexpr int r = decltype(rc)::value;
 #pragma unroll
             for (int i = 0; i < 128; ++i) {
                 const int n = 128 * r + i;
@@ -278,8 +288,10 @@ __device__ __forceinline__ void part1024(const A& in, const Out& o, float* lds, 
                     if ((g & 7) == 7) lng::chunk_fence(o);
                 }
             }
-            if (r == 0) __syncthreads();
-        }
+            if constexpr (r == 0) __syncthreads();
+        };
+        round(std::integral_constant<int, 0>{});
+        round(std::integral_constant<int, 1>{});
     }
 }
 

@@ -447,16 +447,19 @@ __host__ __device__ __forceinline__ void dct4_512_fft(const cf (&t)[128], cf (&f
 // post-twiddle into y (part 2: y[2k] = Y[2k], y[2k+1] = Y[511-2k]; part 3: Y[256+2k],
 // Y[255-2k]).
 template <int P>
+__host__ __device__ __forceinline__ void dct4_512_post_k(const cf& f, const cf& pf, int k, float (&y)[256], twptr tw)
+{
+    const cf c = P == 2 ? cadd(f, pf) : csub(pf, f);
+    const float2 q = tw[TwLayout<1024>::post(512) + k + 128 * (P - 2)];
+    y[2 * k] = c.x * q.x + c.y * q.y;
+    y[2 * k + 1] = c.x * q.y - c.y * q.x;
+}
+template <int P>
 __host__ __device__ __forceinline__ void dct4_512_post(const cf (&f)[128], const cf (&pf)[128], float (&y)[256],
                                                        twptr tw)
 {
 #pragma unroll
-    for (int k = 0; k < 128; ++k) {
-        const cf c = P == 2 ? cadd(f[k], pf[k]) : csub(pf[k], f[k]);
-        const float2 q = tw[TwLayout<1024>::post(512) + k + 128 * (P - 2)];
-        y[2 * k] = c.x * q.x + c.y * q.y;
-        y[2 * k + 1] = c.x * q.y - c.y * q.x;
-    }
+    for (int k = 0; k < 128; ++k) dct4_512_post_k<P>(f[k], pf[k], k, y, tw);
 }
 
 // X index of value s (< 256) of part P's forward output (L = 1024).
