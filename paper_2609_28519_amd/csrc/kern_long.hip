@@ -6,10 +6,11 @@
 //
 // Data between the parts goes through LDS, laid out [value][lane] (consecutive lanes on
 // consecutive words, free of bank conflicts):
-//   * L = 512: one part hands its 256 values to the other (64 KB), which writes the whole
-//     line: the forward's interleaved coefficients of a row (part 1 writes), or the inverse's
-//     x[n] = u[n] + w[n], x[511-n] = u[n] - w[n] (part 0 writes).  A forward column pass needs no exchange: each part writes its
-//     own output rows.
+//   * L = 512: each part hands half of its values to the other (32 KB each) and writes half of
+//     the line, forward, half of the interleaved coefficients (a row's first or second half of
+//     float4 groups; a column's first or second 256 rows); inverse and round trip columns, the
+//     pairs x[n] = u[n] + w[n], x[511-n] = u[n] - w[n] of its half of n.  Inverse and round trip
+//     rows: part 1 hands its 256 values to part 0 (64 KB), which writes the whole row.
 //   * L = 1024: parts 2 and 3 exchange their FFT halves (128 KB); natural-order outputs then
 //     go through LDS in two rounds of 128 KB (a row's forward coefficients by halves of the
 //     row; the inverse recombination by halves of n < 256, four output runs per round, one
@@ -96,51 +97,92 @@ __device__ __forceinline__ void part512(const A& in, const Out& o, float* lds, i
         }
     }
     if constexpr (DIR == DCT2D_FORWARD && COLS) {
-        __syncthreads(); // every part has read the line
+        // part 0 writes output rows 0 .. 255, part 1 rows 256 .. 511 (X[2k] = y0[k], X[2k+1] =
+        // y1[k]), each taking the partner's half of the values through LDS, so only 128 values
+        // per part are held across the barrier (which also waits until every part has read the
+        // line: the pass is in place)
 #pragma unroll
-        for (int k = 0; k < 256; ++k) {
-            o.st(2 * k + P, y[k]);
-            if ((k & 31) == 31) o.refresh();
+        for (int k = 0; k < 128; ++k) {
+            if constexpr (P == 0) ld(lds, k, lane) = y[128 + k];
+            else ld(lds, 128 + k, lane) = y[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 128; ++i) {
+            const int k = 128 * P + i;
+            if constexpr (P == 0) {
+                o.st(2 * k, y[k]);
+                o.st(2 * k + 1, ld(lds, 128 + k, lane));
+            } else {
+                o.st(2 * k, ld(lds, k - 128, lane));
+                o.st(2 * k + 1, y[k]);
+            }
+            if ((i & 15) == 15) o.refresh();
         }
         return;
     }
-    // the forward row is written by part 1 (the lighter transform, so the heavier part 0 holds
-    // nothing past its transform); the inverse by part 0, which holds u
-    constexpr int WRITER = DIR == DCT2D_FORWARD ? 1 : 0;
-    if constexpr (P != WRITER) {
+    if constexpr (DIR == DCT2D_FORWARD) {
+        // rows: each part writes half of the row's float4 groups (part 0 groups 0..63, part 1
+        // groups 64..127), each group X[4g .. 4g+3] = y0[2g], y1[2g], y0[2g+1], y1[2g+1]; each
+        // part hands the partner the half of its values the partner's groups need, so only 128
+        // values per part are held across the barrier
 #pragma unroll
-        for (int k = 0; k < 256; ++k) ld(lds, k, lane) = y[k];
+        for (int k = 0; k < 128; ++k) {
+            if constexpr (P == 0) ld(lds, k, lane) = y[128 + k]; // y0[128 + k] for part 1
+            else ld(lds, 128 + k, lane) = y[k];                  // y1[k] for part 0
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 64; ++i) {
+            const int g = 64 * P + i;
+            if constexpr (P == 0)
+                o.st4(g, y[2 * g], ld(lds, 128 + 2 * g, lane), y[2 * g + 1], ld(lds, 128 + 2 * g + 1, lane));
+            else
+                o.st4(g, ld(lds, 2 * g - 128, lane), y[2 * g], ld(lds, 2 * g + 1 - 128, lane), y[2 * g + 1]);
+        }
+        return;
     }
-    __syncthreads();
-    if constexpr (P == WRITER) {
-        if constexpr (DIR == DCT2D_FORWARD) {
-            // X[2k] from part 0, X[2k+1] = y[k] (own)
+    // inverse and round trip: x[n] = u[n] + w[n], x[511-n] = u[n] - w[n] with u from part 0, w from
+    // part 1
+    if constexpr (COLS) {
+        // part P writes the pairs n in [128 P, 128 P + 128) and hands the partner the half of its
+        // values the partner needs (part 0 u[128 .. 255], part 1 w[0 .. 127]), so only 128
+        // values per part are held across the barrier
 #pragma unroll
-            for (int g = 0; g < 128; ++g)
-                o.st4(g, ld(lds, 2 * g, lane), y[2 * g], ld(lds, 2 * g + 1, lane), y[2 * g + 1]);
-        } else {
-            // x[n] = u[n] + w[n], x[511-n] = u[n] - w[n]; u = y (own), w from part 1
-            if constexpr (COLS) {
+        for (int k = 0; k < 128; ++k) {
+            if constexpr (P == 0) ld(lds, k, lane) = y[128 + k];
+            else ld(lds, 128 + k, lane) = y[k];
+        }
+        __syncthreads();
 #pragma unroll
-                for (int n = 0; n < 256; ++n) {
-                    const float w = ld(lds, n, lane);
-                    o.st(n, y[n] + w);
-                    o.st(511 - n, y[n] - w);
-                    if ((n & 15) == 15) o.refresh();
+        for (int i = 0; i < 128; ++i) {
+            const int n = 128 * P + i;
+            const float u = P == 0 ? y[n] : ld(lds, n - 128, lane);
+            const float w = P == 0 ? ld(lds, 128 + n, lane) : y[n];
+            o.st(n, u + w);
+            o.st(511 - n, u - w);
+            if ((i & 15) == 15) o.refresh();
+        }
+    } else {
+        // rows: part 1 hands w to part 0, which writes the whole row in float4 groups (measured
+        // faster here than splitting the row between the parts)
+        if constexpr (P == 1) {
+#pragma unroll
+            for (int k = 0; k < 256; ++k) ld(lds, k, lane) = y[k];
+        }
+        __syncthreads();
+        if constexpr (P == 0) {
+#pragma unroll
+            for (int g = 0; g < 64; ++g) {
+                float s4[4], d4[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float w = ld(lds, 4 * g + i, lane);
+                    s4[i] = y[4 * g + i] + w;
+                    d4[i] = y[4 * g + i] - w;
                 }
-            } else {
-#pragma unroll
-                for (int g = 0; g < 64; ++g) {
-                    float s[4], d[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const float w = ld(lds, 4 * g + i, lane);
-                        s[i] = y[4 * g + i] + w;
-                        d[i] = y[4 * g + i] - w;
-                    }
-                    o.st4(g, s[0], s[1], s[2], s[3]);
-                    o.st4(127 - g, d[3], d[2], d[1], d[0]);
-                }
+                o.st4(g, s4[0], s4[1], s4[2], s4[3]);
+                o.st4(127 - g, d4[3], d4[2], d4[1], d4[0]);
             }
         }
     }
