@@ -217,6 +217,63 @@ __device__ __forceinline__ void dct4_512_exchange(const cf (&t)[128], float (&y)
     }
 }
 
+// Inverse rows (L = 1024): the coefficients of a row pass through LDS in two halves of 512,
+// element e of the half at ld(lds, e, lane).  Each part loads a quarter of every half as float4
+// groups (groups 32 P .. 32 P + 31 of the half), so every byte of the row is read once; read
+// directly, each part would load one float of every float4 group of the row (its quarter of the
+// coefficients), and the four parts together fetched the row 2.5 times over.  Then each part
+// gathers its own values: parts 0 and 1 X[4k + 2P]; parts 2 and 3 the pair (X[ma], X[mb]) of
+// FFT point i, with ma = 8i + 4(P - 2) + 1 and mb = 1023 - 8i - 4(P - 2), which lie in
+// different halves (ma in the first half for i < 64, mb for i >= 64), so the first half's value
+// is held until the second.  Four workgroup barriers.
+template <int P>
+__device__ __forceinline__ void inv1024_rows_staged(const GRow& X, float* lds, int lane, float (&v)[256],
+                                                    cf (&t)[128], twptr tw)
+{
+    float held[128];
+    auto half = [&](auto hc) {
+        constexpr int h = decltype(hc)::value;
+        constexpr int C = 16;
+        lng::pipelined<32 / C, lng::F4s<C>>(
+            X,
+            [&](auto cc, lng::F4s<C>& b) {
+                constexpr int c = decltype(cc)::value;
+#pragma unroll
+                for (int i = 0; i < C; ++i) b.q[i] = X.g4(128 * h + 32 * P + c * C + i);
+            },
+            [&](auto cc, const lng::F4s<C>& b) {
+                constexpr int c = decltype(cc)::value;
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    const int g = 32 * P + c * C + i;
+                    ld(lds, 4 * g, lane) = b.q[i].x;
+                    ld(lds, 4 * g + 1, lane) = b.q[i].y;
+                    ld(lds, 4 * g + 2, lane) = b.q[i].z;
+                    ld(lds, 4 * g + 3, lane) = b.q[i].w;
+                }
+            });
+        __syncthreads();
+        if constexpr (P < 2) {
+#pragma unroll
+            for (int k = 128 * h; k < 128 * h + 128; ++k) v[k] = ld(lds, 4 * k + 2 * P - 512 * h, lane);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 128; ++i) {
+                const int ma = 8 * i + 4 * (P - 2) + 1, mb = 1023 - 8 * i - 4 * (P - 2);
+                const bool a_first = i < 64;
+                if constexpr (h == 0) held[i] = ld(lds, a_first ? ma : mb, lane);
+                else {
+                    const float late = ld(lds, (a_first ? mb : ma) - 512, lane);
+                    t[i] = lng::pre512<P>(a_first ? held[i] : late, a_first ? late : held[i], i, tw);
+                }
+            }
+        }
+        __syncthreads();
+    };
+    half(std::integral_constant<int, 0>{});
+    half(std::integral_constant<int, 1>{});
+}
+
 template <int DIR, bool COLS, int P, class A>
 __device__ __forceinline__ void part1024(const A& in, const Out& o, float* lds, int lane, twptr tw)
 {
@@ -229,14 +286,22 @@ __device__ __forceinline__ void part1024(const A& in, const Out& o, float* lds, 
             lng::fwd1024_in01<P>(in, v);
             if constexpr (P == 0) dct2_rec<1024, 256>(v, y, tw); else dct4_scaled<1024, 256>(v, y, tw);
         } else {
-            lng::inv1024_in01<P>(in, v);
+            if constexpr (COLS) lng::inv1024_in01<P>(in, v);
+            else {
+                cf unused[128];
+                inv1024_rows_staged<P>(in, lds, lane, v, unused, tw);
+            }
             if constexpr (P == 0) dct3_rec<1024, 256>(v, y, tw); else dct4_scaled<1024, 256>(v, y, tw);
         }
         __syncthreads(); // the exchange of parts 2 and 3
     } else {
         cf t[128];
         if constexpr (DIR == DCT2D_FORWARD) lng::fwd1024_in23<P>(in, t, tw);
-        else lng::inv1024_in23<P>(in, t, tw);
+        else if constexpr (COLS) lng::inv1024_in23<P>(in, t, tw);
+        else {
+            float unused[256];
+            inv1024_rows_staged<P>(in, lds, lane, unused, t, tw);
+        }
         dct4_512_exchange<P>(t, y, lds, lane, tw);
     }
     // every part has read the line (before the exchange barrier)
