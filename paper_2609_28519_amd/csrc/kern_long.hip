@@ -16,8 +16,8 @@
 //     row; the inverse recombination by halves of n < 256, four output runs per round, one
 //     run per part).
 // The round trip runs along rows and then along columns (Q_h^T Q_h X Q_w^T Q_w, the same
-// product as inverse(forward(X))): fused per line for 512, a forward then an inverse pass for
-// 1024.
+// product as inverse(forward(X))), fused per line: each part inverts its own coefficients in
+// registers (for 1024, parts 2 and 3 first regroup their DCT-IV_512 coefficients through LDS).
 #include <hip/hip_runtime.h>
 
 #include "dct1d.hpp"
@@ -277,14 +277,21 @@ __device__ __forceinline__ void inv1024_rows_staged(const GRow& X, float* lds, i
 template <int DIR, bool COLS, int P, class A>
 __device__ __forceinline__ void part1024(const A& in, const Out& o, float* lds, int lane, twptr tw)
 {
-    static_assert(DIR == DCT2D_FORWARD || DIR == DCT2D_INVERSE, "the round trip is two passes");
     part_entry<P>();
     float y[256];
     if constexpr (P < 2) {
         float v[256];
-        if constexpr (DIR == DCT2D_FORWARD) {
+        if constexpr (DIR != DCT2D_INVERSE) {
             lng::fwd1024_in01<P>(in, v);
             if constexpr (P == 0) dct2_rec<1024, 256>(v, y, tw); else dct4_scaled<1024, 256>(v, y, tw);
+            if constexpr (DIR == DCT2D_ROUNDTRIP) {
+                // the inverse of the part's own coefficients, in registers: uu (part 0) or uw
+                twptr tw2 = tw;
+                tw_fence(tw2);
+                if constexpr (P == 0) dct3_rec<1024, 256>(y, v, tw2); else dct4_scaled<1024, 256>(y, v, tw2);
+#pragma unroll
+                for (int n = 0; n < 256; ++n) y[n] = v[n];
+            }
         } else {
             if constexpr (COLS) lng::inv1024_in01<P>(in, v);
             else {
@@ -294,15 +301,42 @@ __device__ __forceinline__ void part1024(const A& in, const Out& o, float* lds, 
             if constexpr (P == 0) dct3_rec<1024, 256>(v, y, tw); else dct4_scaled<1024, 256>(v, y, tw);
         }
         __syncthreads(); // the exchange of parts 2 and 3
+        if constexpr (DIR == DCT2D_ROUNDTRIP) {
+            // parts 2 and 3 redistribute their coefficients and run the inverse exchange
+            __syncthreads();
+            __syncthreads();
+            __syncthreads();
+            __syncthreads();
+        }
     } else {
         cf t[128];
-        if constexpr (DIR == DCT2D_FORWARD) lng::fwd1024_in23<P>(in, t, tw);
+        if constexpr (DIR != DCT2D_INVERSE) lng::fwd1024_in23<P>(in, t, tw);
         else if constexpr (COLS) lng::inv1024_in23<P>(in, t, tw);
         else {
             float unused[256];
             inv1024_rows_staged<P>(in, lds, lane, unused, t, tw);
         }
         dct4_512_exchange<P>(t, y, lds, lane, tw);
+        if constexpr (DIR == DCT2D_ROUNDTRIP) {
+            // round trip: the DCT-IV_512 coefficients Y[j] (= X[2j + 1]) go to LDS slot j (part 2
+            // holds Y[2k] and Y[511-2k] as y[2k], y[2k+1]; part 3 Y[256+2k] and Y[255-2k]), then
+            // each part gathers the inverse's points, Y[j] and Y[511-j] with j = 4i + 2(P - 2),
+            // and the same DCT-IV_512 runs again (its own inverse at this scaling)
+            __syncthreads(); // the partner's FFT half has been read
+#pragma unroll
+            for (int k = 0; k < 128; ++k) {
+                ld(lds, P == 2 ? 2 * k : 256 + 2 * k, lane) = y[2 * k];
+                ld(lds, P == 2 ? 511 - 2 * k : 255 - 2 * k, lane) = y[2 * k + 1];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 128; ++i) {
+                const int j = 4 * i + 2 * (P - 2);
+                t[i] = lng::pre512<P>(ld(lds, j, lane), ld(lds, 511 - j, lane), i, tw);
+            }
+            __syncthreads(); // read before the inverse exchange writes the area
+            dct4_512_exchange<P>(t, y, lds, lane, tw);
+        }
     }
     // every part has read the line (before the exchange barrier)
     if constexpr (DIR == DCT2D_FORWARD && COLS) {
@@ -402,6 +436,20 @@ __device__ __forceinline__ void part1024(const A& in, const Out& o, float* lds, 
     }
 }
 
+// The part of a 1024-point line that this wavefront runs (part is wave-uniform), for the
+// round trip: a plain function, force-inlined; as a lambda the compiler kept this, the largest
+// instantiation, out of line as a call.
+template <int DIR, bool COLS, class A>
+__device__ __forceinline__ void parts1024(const A& in, int part, const Out& o, float* lds, int lane, twptr tw)
+{
+    switch (part) {
+    case 0: part1024<DIR, COLS, 0>(in, o, lds, lane, tw); break;
+    case 1: part1024<DIR, COLS, 1>(in, o, lds, lane, tw); break;
+    case 2: part1024<DIR, COLS, 2>(in, o, lds, lane, tw); break;
+    default: part1024<DIR, COLS, 3>(in, o, lds, lane, tw); break;
+    }
+}
+
 template <int L, int DIR, bool COLS>
 __global__ void __launch_bounds__(kLanes * (L / 256), 1)
 k_long(Addr a, int64_t total, int32_t lpa, int32_t es, int32_t ls, const float2* __restrict__ tw_in)
@@ -427,15 +475,22 @@ k_long(Addr a, int64_t total, int32_t lpa, int32_t es, int32_t ls, const float2*
             if (part == 0) part512<DIR, false, 0>(in, o, lds, lane, tw); else part512<DIR, false, 1>(in, o, lds, lane, tw);
         }
     } else {
-        auto go = [&](const auto& in) {
-            switch (part) {
-            case 0: part1024<DIR, COLS, 0>(in, o, lds, lane, tw); break;
-            case 1: part1024<DIR, COLS, 1>(in, o, lds, lane, tw); break;
-            case 2: part1024<DIR, COLS, 2>(in, o, lds, lane, tw); break;
-            default: part1024<DIR, COLS, 3>(in, o, lds, lane, tw); break;
-            }
-        };
-        if constexpr (COLS) go(GCol{src, es}); else go(GRow{src});
+        if constexpr (DIR == DCT2D_ROUNDTRIP) {
+            if constexpr (COLS) parts1024<DIR, COLS>(GCol{src, es}, part, o, lds, lane, tw);
+            else parts1024<DIR, COLS>(GRow{src}, part, o, lds, lane, tw);
+        } else {
+            // forward and inverse keep the lambda form (inlined there), whose register
+            // allocation measured better (forward rows: 108 B of scratch against 312)
+            auto go = [&](const auto& in) {
+                switch (part) {
+                case 0: part1024<DIR, COLS, 0>(in, o, lds, lane, tw); break;
+                case 1: part1024<DIR, COLS, 1>(in, o, lds, lane, tw); break;
+                case 2: part1024<DIR, COLS, 2>(in, o, lds, lane, tw); break;
+                default: part1024<DIR, COLS, 3>(in, o, lds, lane, tw); break;
+                }
+            };
+            if constexpr (COLS) go(GCol{src, es}); else go(GRow{src});
+        }
     }
 }
 
@@ -472,11 +527,7 @@ int axis_pass(const DeviceTables* t, const Addr& a, int64_t batch, int rows, int
     if (len == 1024) {
         if (dir == DCT2D_FORWARD) return long_pass<1024, DCT2D_FORWARD>(t, a, batch, lpa, es, ls, column_pass, s);
         if (dir == DCT2D_INVERSE) return long_pass<1024, DCT2D_INVERSE>(t, a, batch, lpa, es, ls, column_pass, s);
-        // round trip: forward, then inverse in place
-        const int rc = long_pass<1024, DCT2D_FORWARD>(t, a, batch, lpa, es, ls, column_pass, s);
-        if (rc != DCT2D_OK) return rc;
-        const Addr in_place{a.out, a.out, a.out_stride, a.out_stride, a.out_idx, a.out_idx, a.out_slot, a.out_slot};
-        return long_pass<1024, DCT2D_INVERSE>(t, in_place, batch, lpa, es, ls, column_pass, s);
+        return long_pass<1024, DCT2D_ROUNDTRIP>(t, a, batch, lpa, es, ls, column_pass, s);
     }
     return DCT2D_ERR_SIZE;
 }
