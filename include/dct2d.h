@@ -37,7 +37,7 @@
  * split into its even/odd halves (Section 2.2) down to length-256 DCT-II/III and DCT-IV
  * transforms (the DCT-IV of a 512-point half through a 128-point complex FFT), each half
  * held by one wavefront and the halves combined through LDS.  Each pass reads and writes
- * the array once (the round trip of a 1024 axis: forward then inverse, two passes).  Float32
+ * the array once; the round trip is fused per line (forward, then inverse, in one pass).  Float32
  * path only (any other precision: DCT2D_ERR_PRECISION).  The variant, autotuner and
  * filter calls cover axes up to 256.  Any other length returns DCT2D_ERR_SIZE: like the
  * paper (Section 7.1) the basic API rejects non-power-of-two axes instead of
