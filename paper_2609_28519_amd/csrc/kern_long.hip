@@ -284,14 +284,6 @@ __device__ __forceinline__ void part1024(const A& in, const Out& o, float* lds, 
         if constexpr (DIR != DCT2D_INVERSE) {
             lng::fwd1024_in01<P>(in, v);
             if constexpr (P == 0) dct2_rec<1024, 256>(v, y, tw); else dct4_scaled<1024, 256>(v, y, tw);
-            if constexpr (DIR == DCT2D_ROUNDTRIP) {
-                // the inverse of the part's own coefficients, in registers: uu (part 0) or uw
-                twptr tw2 = tw;
-                tw_fence(tw2);
-                if constexpr (P == 0) dct3_rec<1024, 256>(y, v, tw2); else dct4_scaled<1024, 256>(y, v, tw2);
-#pragma unroll
-                for (int n = 0; n < 256; ++n) y[n] = v[n];
-            }
         } else {
             if constexpr (COLS) lng::inv1024_in01<P>(in, v);
             else {
@@ -302,6 +294,14 @@ __device__ __forceinline__ void part1024(const A& in, const Out& o, float* lds, 
         }
         __syncthreads(); // the exchange of parts 2 and 3
         if constexpr (DIR == DCT2D_ROUNDTRIP) {
+            // the inverse of the part's own coefficients, in registers (uu for part 0, uw for
+            // part 1), done here, while parts 2 and 3 regroup their coefficients and run their
+            // second exchange, instead of before the first barrier
+            twptr tw2 = tw;
+            tw_fence(tw2);
+            if constexpr (P == 0) dct3_rec<1024, 256>(y, v, tw2); else dct4_scaled<1024, 256>(y, v, tw2);
+#pragma unroll
+            for (int n = 0; n < 256; ++n) y[n] = v[n];
             // parts 2 and 3 redistribute their coefficients and run the inverse exchange
             __syncthreads();
             __syncthreads();
