@@ -14,7 +14,7 @@
 //   * L = 1024: parts 2 and 3 exchange their FFT halves (128 KB); natural-order outputs then
 //     go through LDS in two rounds of 128 KB (a row's forward coefficients by halves of the
 //     row; the inverse recombination by halves of n < 256, four output runs per round, one
-//     run per part).
+//     run per part).  The inverse row pass also stages its input through LDS by half-rows.
 // The round trip runs along rows and then along columns (Q_h^T Q_h X Q_w^T Q_w, the same
 // product as inverse(forward(X))), fused per line: each part inverts its own coefficients in
 // registers (for 1024, parts 2 and 3 first regroup their DCT-IV_512 coefficients through LDS).
